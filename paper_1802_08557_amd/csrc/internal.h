@@ -1,0 +1,84 @@
+// internal.h -- structures shared by the host runtime and the HIP kernels.
+// Not part of the public ABI (include/lpbatch.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpb {
+
+// Tolerances and limits of one solve (the public lp_options with defaults filled in).
+struct SolveParams {
+    double tol_piv;    // a pivot-column entry must exceed this to be eligible (Step 2)
+    double tol_opt;    // reduced costs above tol_opt * max(1, |c|_inf) may enter (Step 1)
+    double tol_feas;   // Phase I optimum below -tol_feas * (1 + |b|_inf) means infeasible
+    int32_t k_deg;     // consecutive degenerate pivots before Bland's rule; <= 0: never
+    int32_t max_iters; // pivot cap over both phases; <= 0: 50 * (m + #columns)
+};
+
+// Everything one launch of the simplex kernel needs.  Device pointers unless noted.
+struct SolveArgs {
+    int64_t num;              // work items in this launch (upper bound if num_dev is set)
+    const int32_t *ids;       // work item -> LP index; null: identity
+    const int32_t *num_dev;   // optional device-side item count (<= num)
+    const double *A, *b, *c;  // batch data, layout of include/lpbatch.h
+    const int8_t *sense;
+    int32_t um, un;           // > 0: every LP is um x un (offsets computed, m/n/offsets unused)
+    const int32_t *m, *n;     // per-LP sizes when not uniform
+    const int64_t *aoff, *roff, *coff;
+    int32_t *status;          // outputs
+    double *x, *obj;
+    int32_t *stats;           // optional [num_lps][8]
+    int32_t *basis_out;       // optional [sum m]: final basis (Bland index, -1 dropped row)
+    int32_t *enter_out;       // optional [num_lps]: entering Bland index at UNBOUNDED
+    char *scratch;            // HBM tableau slots, one per workgroup of the launch
+    int64_t slot_bytes;
+    int32_t *queue;           // work counter, zeroed before the launch
+    int32_t lds_bytes;        // dynamic LDS of each workgroup
+    int32_t force_hbm;        // 1: never keep the tableau in LDS
+    SolveParams prm;
+};
+
+// Bland index convention shared by every kernel: structural j -> j, the
+// slack/surplus of row i -> n + i, the artificial of row i -> n + m + i.
+
+// Launchers (simplex_kernels.hip).  Return the hipError_t of the launch.
+hipError_t launch_zero_i32(int32_t *p, int count, hipStream_t s);
+hipError_t launch_simplex(bool fp32, int nt, const SolveArgs &a, int grid, hipStream_t s);
+// Workgroups of the simplex kernel that fit one CU with this LDS (occupancy query).
+int simplex_blocks_per_cu(bool fp32, int nt, int lds_bytes);
+// Bytes of the kernel's LDS control block for the given tableau precision.
+int64_t simplex_ctrl_bytes(bool fp32);
+// Allows every simplex kernel instantiation up to max_lds bytes of dynamic LDS.
+hipError_t simplex_configure(int max_lds);
+
+// Size of the LDS control block + index arrays + pivot row/column buffers for an
+// LP with m rows and at most ncol_max non-basic columns, and the byte offset where
+// an LDS-resident tableau would start.  Host and device compute the same layout.
+__host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~int64_t(15); }
+
+struct LdsLayout {
+    int64_t ctrl, basis, nonb, rowf, colrow, pcol, prow, tab, end_aux;
+};
+
+// ctrl_bytes: size of the control block (type dependent, passed by the caller).
+__host__ __device__ inline LdsLayout lds_layout(int m, int ncol_max, int64_t tsize, int64_t ctrl_bytes)
+{
+    LdsLayout L;
+    L.ctrl = 0;
+    L.basis = align16(ctrl_bytes);
+    L.nonb = align16(L.basis + 4 * (int64_t)m);
+    L.rowf = align16(L.nonb + 4 * (int64_t)ncol_max);
+    L.colrow = align16(L.rowf + 4 * (int64_t)m);
+    L.pcol = align16(L.colrow + 4 * (int64_t)m);
+    L.prow = align16(L.pcol + tsize * (int64_t)(m + 1));
+    L.tab = align16(L.prow + tsize * (int64_t)(ncol_max + 1));
+    L.end_aux = L.tab;
+    return L;
+}
+
+// Row stride of a tableau with C = (non-basic columns + 1) entries per row: odd,
+// so that walking a column of an LDS-resident tableau spreads over the banks.
+__host__ __device__ inline int tableau_ld(int C) { return C | 1; }
+
+}  // namespace lpb

@@ -1,0 +1,553 @@
+// simplex_kernels.hip -- the batched dense-tableau simplex for gfx950.
+//
+// One workgroup solves one LP at a time and pops the next LP from a work
+// counter (a persistent launch sized to what the device holds at once).  The
+// paper maps one CUDA block to one LP (Sec. 5.1, load balancing) and uses the
+// block's threads inside the tableau; here a workgroup of NT threads (one or
+// more 64-wide wavefronts) does the same, with the tableau kept in LDS when it
+// fits the launch's LDS budget and in an HBM scratch slot of the workgroup
+// otherwise.
+//
+// The tableau is the condensed ("exchange") form of the paper's Sec. 4.1
+// tableau: the m basic columns are unit vectors and are not stored, so a row
+// holds the N non-basic columns and the right-hand side, and a pivot swaps the
+// entering and leaving variables' columns in place.  Rows 0..m-1 are the
+// constraints, row m the objective: reduced costs d_j (entering candidates
+// have d_j > 0) and, in the rhs cell, minus the current objective value.
+// basis[i] / nonb[j] hold the Bland index of the variable of row i / column j.
+//
+// Per iteration (Sec. 4.1):
+//   Step 1 (pricing): argmax of d_j > eps_opt over eligible columns, ties to
+//     the smallest Bland index; Bland's smallest-index rule after k_deg
+//     consecutive degenerate pivots, until a pivot makes progress.
+//   Step 2 (ratio): argmin of max(b_i, 0) / a_ie over rows with a_ie > tol_piv,
+//     ties to the smallest Bland index of the basic variable; none: unbounded.
+//     Wavefront butterfly reductions on (key, Bland index) pairs stand in for
+//     the paper's Data[]/Indices[] arrays, with +inf as the "MAX" sentinel.
+//   Step 3 (pivot): pivot row / PE; every other row (objective included) minus
+//     a_ie times the new pivot row (Listing 1); the entering column becomes the
+//     leaving variable's column: 1/PE in the pivot row, -a_ie/PE elsewhere.
+//     Every element is rewritten with one fma, the same expression wherever
+//     the tableau lives, so results do not depend on the placement or the
+//     workgroup size.
+// Phase I (Sec. 4) maximises -(sum of artificials) when some row needs one;
+// basic artificials at zero are driven out and redundant rows dropped, then
+// Phase II prices c out over the basis and continues.
+#include <math.h>
+
+#include "internal.h"
+
+namespace lpb {
+namespace {
+
+constexpr int LE = 0, GE = 1, EQ = 2;
+constexpr int ST_OPTIMAL = 0, ST_INFEASIBLE = 1, ST_UNBOUNDED = 2, ST_ITER = 3,
+              ST_NUMERICAL = 4, ST_INVALID = 5;
+constexpr int BIG = 0x7fffffff;
+constexpr int ROW_NEG = 1, ROW_DEAD = 8;
+
+template <typename T> __device__ __forceinline__ T t_inf();
+template <> __device__ __forceinline__ float t_inf<float>() { return __builtin_inff(); }
+template <> __device__ __forceinline__ double t_inf<double>() { return __builtin_inf(); }
+
+template <typename T>
+struct Ctrl {
+    int ng, nart, neq, bad;
+    int next;
+    int pad[3];
+    double bnorm, cnorm;
+    T rv[16];
+    int ri[16];
+    int rp[16];
+    double rd[16];
+};
+
+__device__ __forceinline__ int row_sense(int f) { return (f >> 1) & 3; }
+
+// ---- reductions ------------------------------------------------------------
+
+// Lexicographic argmin over the wavefront of (k1, k2), carrying a position.
+// Keys are unique or all-invalid, so every lane ends with the same winner.
+template <typename T>
+__device__ __forceinline__ void wave_argmin(T &k1, int &k2, int &p)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        T o1 = __shfl_xor(k1, off);
+        int o2 = __shfl_xor(k2, off);
+        int op = __shfl_xor(p, off);
+        if (o1 < k1 || (o1 == k1 && o2 < k2)) { k1 = o1; k2 = o2; p = op; }
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void block_argmin(T &k1, int &k2, int &p, Ctrl<T> *sh)
+{
+    wave_argmin(k1, k2, p);
+    if constexpr (NT > 64) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) { sh->rv[w] = k1; sh->ri[w] = k2; sh->rp[w] = p; }
+        __syncthreads();
+        k1 = sh->rv[0]; k2 = sh->ri[0]; p = sh->rp[0];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) {
+            T o1 = sh->rv[q];
+            int o2 = sh->ri[q];
+            if (o1 < k1 || (o1 == k1 && o2 < k2)) { k1 = o1; k2 = o2; p = sh->rp[q]; }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ double block_max(double v, Ctrl<T> *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if constexpr (NT > 64) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) sh->rd[w] = v;
+        __syncthreads();
+        v = sh->rd[0];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) v = fmax(v, sh->rd[q]);
+        __syncthreads();
+    }
+    return v;
+}
+
+// ---- one LP ------------------------------------------------------------------
+
+template <typename T, int NT>
+struct LP {
+    // geometry
+    int m, n, N, C, ld, nart;
+    int64_t k, ro, co;
+    const double *A, *b, *c;
+    // LDS arrays
+    Ctrl<T> *sh;
+    int *basis, *nonb, *rowf, *colrow;
+    T *pcol, *prow;
+    T *tab;  // LDS or HBM
+    // counters (uniform across the workgroup)
+    int iters, it1, degp, cap;
+};
+
+// Step 3: pivot on (l, e).  Every thread takes part; ends with a barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int W = NT / 64;
+    T *tab = P.tab;
+    const int ld = P.ld, C = P.C, m = P.m;
+    const T pe = tab[(int64_t)l * ld + e];
+    for (int j = tid; j < C; j += NT)
+        P.prow[j] = (j == e) ? T(1) / pe : tab[(int64_t)l * ld + j] / pe;
+    for (int i = tid; i <= m; i += NT)
+        P.pcol[i] = (i < m && (P.rowf[i] & ROW_DEAD)) ? T(0) : tab[(int64_t)i * ld + e];
+    __syncthreads();
+    for (int i = wave; i <= m; i += W) {
+        T *row = tab + (int64_t)i * ld;
+        if (i == l) {
+            for (int j = lane; j < C; j += 64) row[j] = P.prow[j];
+        } else {
+            const T f = P.pcol[i];
+            for (int j = lane; j < C; j += 64) {
+                const T base = (j == e) ? T(0) : row[j];
+                row[j] = fma(-f, P.prow[j], base);
+            }
+        }
+    }
+    if (tid == 0) {
+        const int t = P.basis[l];
+        P.basis[l] = P.nonb[e];
+        P.nonb[e] = t;
+    }
+    __syncthreads();
+}
+
+// Steps 1-3 until a halt condition.  Returns ST_OPTIMAL, ST_UNBOUNDED or ST_ITER;
+// *enter receives the entering Bland index when unbounded.
+template <typename T, int NT>
+__device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParams &prm, int *enter)
+{
+    const int tid = threadIdx.x;
+    const int m = P.m, N = P.N, ld = P.ld, nm = P.n + P.m;
+    const T tol_piv = T(prm.tol_piv);
+    T *tab = P.tab;
+    int deg_run = 0;
+    for (;;) {
+        if (P.iters >= P.cap) return ST_ITER;
+        const bool bland = prm.k_deg > 0 && deg_run >= prm.k_deg;
+        // Step 1: entering column.
+        T k1 = t_inf<T>();
+        int k2 = BIG, p = -1;
+        const T *obj = tab + (int64_t)m * ld;
+        for (int j = tid; j < N; j += NT) {
+            const T d = obj[j];
+            const int bj = P.nonb[j];
+            if (d > eps_opt && bj < nm) {
+                const T key = bland ? T(0) : -d;
+                if (key < k1 || (key == k1 && bj < k2)) { k1 = key; k2 = bj; p = j; }
+            }
+        }
+        block_argmin<T, NT>(k1, k2, p, P.sh);
+        if (p < 0) return ST_OPTIMAL;
+        const int e = p;
+        // Step 2: leaving row.
+        k1 = t_inf<T>(); k2 = BIG; p = -1;
+        for (int i = tid; i < m; i += NT) {
+            if (P.rowf[i] & ROW_DEAD) continue;
+            const T a = tab[(int64_t)i * ld + e];
+            if (a > tol_piv) {
+                const T bi = tab[(int64_t)i * ld + N];
+                const T th = (bi > T(0) ? bi : T(0)) / a;
+                const int bb = P.basis[i];
+                if (th < k1 || (th == k1 && bb < k2)) { k1 = th; k2 = bb; p = i; }
+            }
+        }
+        block_argmin<T, NT>(k1, k2, p, P.sh);
+        if (p < 0) { *enter = P.nonb[e]; return ST_UNBOUNDED; }
+        if (k1 == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
+        pivot<T, NT>(P, p, e);
+        ++P.iters;
+    }
+}
+
+// Solve LP k with the tableau at P.tab (LDS or HBM).  Row classification
+// (rowf, colrow, Ctrl counts) has been done by the caller.
+template <typename T, int NT>
+__device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int placement)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int W = NT / 64;
+    const int m = P.m, n = P.n, N = P.N, C = P.C, ld = P.ld;
+    Ctrl<T> *sh = P.sh;
+    T *tab = P.tab;
+
+    // A1/A2: non-basic and basic index arrays, then the tableau rows
+    // (sign-normalised so every rhs is >= 0, with a -1 surplus entry per >= row).
+    for (int j = tid; j < N; j += NT) P.nonb[j] = (j < n) ? j : n + P.colrow[j - n];
+    for (int i = tid; i < m; i += NT)
+        P.basis[i] = (row_sense(P.rowf[i]) == LE) ? n + i : n + m + i;
+    bool bad = false;
+    for (int i = wave; i < m; i += W) {
+        const double sg = (P.rowf[i] & ROW_NEG) ? -1.0 : 1.0;
+        const double *Ai = P.A + (int64_t)i * n;
+        T *row = tab + (int64_t)i * ld;
+        for (int j = lane; j < C; j += 64) {
+            double v;
+            if (j < n) {
+                const double aij = Ai[j];
+                bad |= !isfinite(aij);
+                v = sg * aij;
+            } else if (j < N) {
+                v = (P.colrow[j - n] == i) ? -1.0 : 0.0;
+            } else {
+                v = sg * P.b[i];
+            }
+            row[j] = T(v);
+        }
+    }
+    double cmax = 0.0;
+    for (int j = tid; j < n; j += NT) {
+        const double cj = P.c[j];
+        bad |= !isfinite(cj);
+        cmax = fmax(cmax, fabs(cj));
+    }
+    if (bad) sh->bad = 1;
+    double bmax = 0.0;
+    for (int i = tid; i < m; i += NT) bmax = fmax(bmax, fabs(P.b[i]));
+    __syncthreads();
+    const double cnorm = block_max<T, NT>(cmax, sh);
+    const double bnorm = block_max<T, NT>(bmax, sh);
+    int status = ST_OPTIMAL, enter = -1;
+    const bool invalid = sh->bad != 0;
+    P.iters = 0; P.it1 = 0; P.degp = 0;
+    P.cap = a.prm.max_iters > 0 ? a.prm.max_iters
+                                : 50 * (m + n + (m - sh->neq) + P.nart);
+
+    if (invalid) {
+        status = ST_INVALID;
+    } else {
+        if (P.nart > 0) {
+            // Phase I objective row: the sum of the artificial rows (in row order).
+            double dmax = 0.0;
+            for (int j = tid; j < C; j += NT) {
+                T acc = T(0);
+                for (int i = 0; i < m; ++i)
+                    if (row_sense(P.rowf[i]) != LE) acc += tab[(int64_t)i * ld + j];
+                tab[(int64_t)m * ld + j] = acc;
+                if (j < N) dmax = fmax(dmax, fabs(double(acc)));
+            }
+            __syncthreads();
+            const double dscale = fmax(1.0, block_max<T, NT>(dmax, sh));
+            const int r = simplex<T, NT>(P, T(a.prm.tol_opt * dscale), a.prm, &enter);
+            P.it1 = P.iters;
+            enter = -1;
+            if (r == ST_ITER) status = ST_ITER;
+            else if (r == ST_UNBOUNDED) status = ST_NUMERICAL;
+            else {
+                const double wstar = -double(tab[(int64_t)m * ld + N]);
+                if (wstar < -a.prm.tol_feas * (1.0 + bnorm)) status = ST_INFEASIBLE;
+            }
+            if (status == ST_OPTIMAL) {
+                // Drive basic artificials out, in row order; drop redundant rows.
+                const T tol_piv = T(a.prm.tol_piv);
+                for (int i = 0; i < m; ++i) {
+                    if (P.basis[i] < n + m) continue;
+                    T k1 = T(0);
+                    int k2 = BIG, p = -1;
+                    for (int j = tid; j < N; j += NT) {
+                        const int bj = P.nonb[j];
+                        if (bj < n + m && fabs(tab[(int64_t)i * ld + j]) > tol_piv && bj < k2) {
+                            k2 = bj; p = j;
+                        }
+                    }
+                    block_argmin<T, NT>(k1, k2, p, sh);
+                    if (p >= 0) {
+                        pivot<T, NT>(P, i, p);
+                    } else {
+                        if (tid == 0) P.rowf[i] |= ROW_DEAD;
+                        __syncthreads();
+                    }
+                }
+            }
+        }
+        if (status == ST_OPTIMAL) {
+            // Phase II objective row: c priced out over the current basis.
+            for (int i = tid; i < m; i += NT) {
+                const int bv = P.basis[i];
+                P.pcol[i] = ((P.rowf[i] & ROW_DEAD) || bv >= n) ? T(0) : T(P.c[bv]);
+            }
+            __syncthreads();
+            for (int j = tid; j < C; j += NT) {
+                const int bj = (j < N) ? P.nonb[j] : BIG;
+                T acc = (bj < n) ? T(P.c[bj]) : T(0);
+                for (int i = 0; i < m; ++i) {
+                    const T cb = P.pcol[i];
+                    if (cb != T(0)) acc = fma(-cb, tab[(int64_t)i * ld + j], acc);
+                }
+                tab[(int64_t)m * ld + j] = acc;
+            }
+            __syncthreads();
+            status = simplex<T, NT>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
+        }
+    }
+
+    // A8: extraction.  x_j = rhs of the row where j is basic, else 0;
+    // objective recomputed in FP64 from the input c by wavefront 0 in a fixed order.
+    T *xv = P.prow;  // reuse as an n-vector
+    for (int j = tid; j < n; j += NT) xv[j] = T(0);
+    __syncthreads();
+    int nbs = 0;
+    if (status == ST_OPTIMAL) {
+        for (int i = tid; i < m; i += NT) {
+            const int bv = P.basis[i];
+            if (bv < n && !(P.rowf[i] & ROW_DEAD)) xv[bv] = tab[(int64_t)i * ld + N];
+        }
+    }
+    __syncthreads();
+    double *x = a.x + P.co;
+    if (status == ST_OPTIMAL) {
+        for (int j = tid; j < n; j += NT) x[j] = double(xv[j]);
+    } else {
+        for (int j = tid; j < n; j += NT) x[j] = __builtin_nan("");
+    }
+    if (wave == 0) {
+        double z = 0.0;
+        for (int j = lane; j < n; j += 64) {
+            const double xj = double(xv[j]);
+            z = fma(P.c[j], xj, z);
+            nbs += (xj != 0.0);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            z += __shfl_xor(z, off);
+            nbs += __shfl_xor(nbs, off);
+        }
+        if (lane == 0) {
+            double objv = z;
+            if (status == ST_UNBOUNDED) objv = __builtin_inf();
+            else if (status != ST_OPTIMAL) objv = __builtin_nan("");
+            a.obj[P.k] = objv;
+            a.status[P.k] = status;
+            if (a.enter_out) a.enter_out[P.k] = (status == ST_UNBOUNDED) ? enter : -1;
+            if (a.stats) {
+                int32_t *st = a.stats + 8 * P.k;
+                st[0] = P.it1;
+                st[1] = P.iters - P.it1;
+                st[2] = P.degp;
+                st[3] = 0;
+                st[4] = 0;
+                st[5] = 0;
+                st[6] = placement;
+                st[7] = nbs;
+            }
+        }
+    }
+    if (a.basis_out)
+        for (int i = tid; i < m; i += NT)
+            a.basis_out[P.ro + i] = (P.rowf[i] & ROW_DEAD) ? -1 : P.basis[i];
+    __syncthreads();
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    Ctrl<T> *sh = reinterpret_cast<Ctrl<T> *>(smem);
+    const int64_t total = a.num_dev ? int64_t(*a.num_dev) : a.num;
+    int64_t item = blockIdx.x;
+    while (item < total) {
+        if (tid == 0) sh->next = gridDim.x + atomicAdd(a.queue, 1);
+        const int64_t k = a.ids ? int64_t(a.ids[item]) : item;
+        LP<T, NT> P;
+        P.k = k;
+        if (a.um > 0) {
+            P.m = a.um; P.n = a.un;
+            P.A = a.A + k * int64_t(a.um) * a.un;
+            P.ro = k * a.um;
+            P.co = k * a.un;
+        } else {
+            P.m = a.m[k]; P.n = a.n[k];
+            P.A = a.A + a.aoff[k];
+            P.ro = a.roff[k];
+            P.co = a.coff[k];
+        }
+        P.b = a.b + P.ro;
+        P.c = a.c + P.co;
+        const int m = P.m, n = P.n;
+        const int8_t *sense = a.sense + P.ro;
+        LdsLayout L = lds_layout(m, n + m, sizeof(T), sizeof(Ctrl<T>));
+        P.sh = sh;
+        P.basis = reinterpret_cast<int *>(smem + L.basis);
+        P.nonb = reinterpret_cast<int *>(smem + L.nonb);
+        P.rowf = reinterpret_cast<int *>(smem + L.rowf);
+        P.colrow = reinterpret_cast<int *>(smem + L.colrow);
+        P.pcol = reinterpret_cast<T *>(smem + L.pcol);
+        P.prow = reinterpret_cast<T *>(smem + L.prow);
+
+        // A1: sign-normalise and classify rows (sense after flipping rows with b < 0).
+        if (tid == 0) sh->bad = 0;
+        __syncthreads();
+        bool bad = false;
+        for (int i = tid; i < m; i += NT) {
+            const double bi = P.b[i];
+            const int s = sense[i];
+            bad |= !isfinite(bi) || s < LE || s > EQ;
+            const bool neg = bi < 0.0;
+            int sen = (s < LE || s > EQ) ? LE : s;
+            if (neg && sen != EQ) sen = (sen == LE) ? GE : LE;
+            P.rowf[i] = (neg ? ROW_NEG : 0) | (sen << 1);
+        }
+        if (bad) sh->bad = 1;
+        __syncthreads();
+        // Surplus columns of >= rows in row order (wavefront ballots), counts.
+        if (wave == 0) {
+            int ng = 0, nart = 0, neq = 0;
+            for (int i0 = 0; i0 < m; i0 += 64) {
+                const int i = i0 + lane;
+                const int sen = (i < m) ? row_sense(P.rowf[i]) : LE;
+                const uint64_t ge = __ballot(i < m && sen == GE);
+                const uint64_t ar = __ballot(i < m && sen != LE);
+                const uint64_t eq = __ballot(i < m && sen == EQ);
+                if (i < m && sen == GE)
+                    P.colrow[ng + __popcll(ge & ((uint64_t(1) << lane) - 1))] = i;
+                ng += __popcll(ge);
+                nart += __popcll(ar);
+                neq += __popcll(eq);
+            }
+            if (lane == 0) { sh->ng = ng; sh->nart = nart; sh->neq = neq; }
+        }
+        __syncthreads();
+        P.N = n + sh->ng;
+        P.C = P.N + 1;
+        P.ld = tableau_ld(P.C);
+        P.nart = sh->nart;
+        const int64_t tab_bytes = int64_t(m + 1) * P.ld * int64_t(sizeof(T));
+        const bool in_lds = !a.force_hbm && L.tab + tab_bytes <= int64_t(a.lds_bytes);
+        if (in_lds) {
+            P.tab = reinterpret_cast<T *>(smem + L.tab);
+            solve_lp<T, NT>(P, a, 1);
+        } else {
+            P.tab = reinterpret_cast<T *>(a.scratch + int64_t(blockIdx.x) * a.slot_bytes);
+            solve_lp<T, NT>(P, a, 2);
+        }
+        item = sh->next;
+        __syncthreads();
+    }
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+template <typename T, int NT>
+hipError_t launch_t(const SolveArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((simplex_kernel<T, NT>), dim3(grid), dim3(NT), a.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+int occ_t(int lds)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)simplex_kernel<T, NT>,
+                                                     NT, lds) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+}  // namespace
+
+hipError_t launch_zero_i32(int32_t *p, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_simplex(bool fp32, int nt, const SolveArgs &a, int grid, hipStream_t s)
+{
+    switch (nt) {
+    case 64: return fp32 ? launch_t<float, 64>(a, grid, s) : launch_t<double, 64>(a, grid, s);
+    case 128: return fp32 ? launch_t<float, 128>(a, grid, s) : launch_t<double, 128>(a, grid, s);
+    case 256: return fp32 ? launch_t<float, 256>(a, grid, s) : launch_t<double, 256>(a, grid, s);
+    case 512: return fp32 ? launch_t<float, 512>(a, grid, s) : launch_t<double, 512>(a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int64_t simplex_ctrl_bytes(bool fp32) { return fp32 ? sizeof(Ctrl<float>) : sizeof(Ctrl<double>); }
+
+hipError_t simplex_configure(int max_lds)
+{
+    const void *fns[] = {
+        (const void *)simplex_kernel<float, 64>, (const void *)simplex_kernel<double, 64>,
+        (const void *)simplex_kernel<float, 128>, (const void *)simplex_kernel<double, 128>,
+        (const void *)simplex_kernel<float, 256>, (const void *)simplex_kernel<double, 256>,
+        (const void *)simplex_kernel<float, 512>, (const void *)simplex_kernel<double, 512>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int simplex_blocks_per_cu(bool fp32, int nt, int lds)
+{
+    switch (nt) {
+    case 64: return fp32 ? occ_t<float, 64>(lds) : occ_t<double, 64>(lds);
+    case 128: return fp32 ? occ_t<float, 128>(lds) : occ_t<double, 128>(lds);
+    case 256: return fp32 ? occ_t<float, 256>(lds) : occ_t<double, 256>(lds);
+    case 512: return fp32 ? occ_t<float, 512>(lds) : occ_t<double, 512>(lds);
+    default: return 0;
+    }
+}
+
+}  // namespace lpb

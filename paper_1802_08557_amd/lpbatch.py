@@ -1,0 +1,204 @@
+"""Python binding of the C-ABI library ``liblpbatch.so`` (include/lpbatch.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  Batch arrays are torch tensors on the GPU (PyTorch supplies device
+memory and streams); m[] and n[] are host int32 arrays.  If the library is not
+built this module raises on first use -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpbatch.so")
+
+LP_LE, LP_GE, LP_EQ = 0, 1, 2
+OPTIMAL, INFEASIBLE, UNBOUNDED, ITERATION_LIMIT, NUMERICAL, INVALID_INPUT = range(6)
+PREC_FP64, PREC_FP32_CERT64 = 0, 1
+PLACE_AUTO, PLACE_LDS, PLACE_HBM = 0, 1, 2
+FLAG_SYNC, FLAG_TIME_KERNELS = 1, 2
+STATS_WIDTH = 8
+LP_OK, LP_ERR_ARG, LP_ERR_NOMEM, LP_ERR_HIP = 0, -1, -2, -3
+
+# Every symbol include/lpbatch.h declares.
+EXPORTS = ("lp_batch_solve", "lp_ctx_create", "lp_ctx_destroy", "lp_options_init",
+           "lp_batch_solve_ex", "lp_ctx_kernel_times", "lp_last_error")
+
+
+class LPOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("tol_piv", ctypes.c_double), ("tol_opt", ctypes.c_double),
+                ("tol_feas", ctypes.c_double), ("k_deg", ctypes.c_int32),
+                ("placement", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("stats", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+class LPBatchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblpbatch error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Open liblpbatch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1802_08557_amd.build_lib` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.lp_batch_solve.argtypes = [i64] + [vp] * 9
+    lib.lp_batch_solve.restype = i32
+    lib.lp_ctx_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.lp_ctx_create.restype = i32
+    lib.lp_ctx_destroy.argtypes = [vp]
+    lib.lp_ctx_destroy.restype = None
+    lib.lp_options_init.argtypes = [ctypes.POINTER(LPOptions)]
+    lib.lp_options_init.restype = None
+    lib.lp_batch_solve_ex.argtypes = [vp, i64] + [vp] * 9 + [ctypes.POINTER(LPOptions)]
+    lib.lp_batch_solve_ex.restype = i32
+    lib.lp_ctx_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p),
+                                        ctypes.POINTER(ctypes.c_float), i32]
+    lib.lp_ctx_kernel_times.restype = i32
+    lib.lp_last_error.argtypes = []
+    lib.lp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().lp_last_error().decode()
+
+
+def _check(rc):
+    if rc != LP_OK:
+        raise LPBatchError(rc, last_error())
+    return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class DeviceBatch:
+    """A batch resident on the GPU: A, b, c (float64), sense (int8) as torch
+    tensors, m, n as host int32 numpy arrays."""
+    A: object
+    b: object
+    c: object
+    sense: object
+    m: np.ndarray
+    n: np.ndarray
+
+    @property
+    def num_lps(self):
+        return int(self.m.shape[0])
+
+    @classmethod
+    def from_host(cls, batch, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        return cls(t(batch.A, np.float64), t(batch.b, np.float64), t(batch.c, np.float64),
+                   t(batch.sense, np.int8), np.ascontiguousarray(batch.m, np.int32),
+                   np.ascontiguousarray(batch.n, np.int32))
+
+
+@dataclass
+class Solution:
+    status: object   # torch int32 [N]
+    x: object        # torch float64 [sum n]
+    obj: object      # torch float64 [N]
+    stats: object    # torch int32 [N, 8] or None
+
+
+class Context:
+    """An lp_ctx on one device (scratch, plans, timing events)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.lp_ctx_create(ctypes.byref(h), int(device)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.lp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, batch: DeviceBatch, *, precision=PREC_FP64, max_iters=0, tol_piv=0.0,
+              tol_opt=0.0, tol_feas=0.0, k_deg=50, placement=PLACE_AUTO, block_threads=0,
+              stats=False, stream=None, sync=False, time_kernels=False, out=None) -> Solution:
+        """Queue lp_batch_solve_ex on `stream` (default: torch's current stream)."""
+        import torch
+        dev = batch.A.device
+        N = batch.num_lps
+        if out is None:
+            status = torch.empty(N, dtype=torch.int32, device=dev)
+            x = torch.empty(int(batch.n.sum()), dtype=torch.float64, device=dev)
+            obj = torch.empty(N, dtype=torch.float64, device=dev)
+            st = torch.empty((N, STATS_WIDTH), dtype=torch.int32, device=dev) if stats else None
+        else:
+            status, x, obj, st = out.status, out.x, out.obj, out.stats
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        o = LPOptions()
+        self.lib.lp_options_init(ctypes.byref(o))
+        o.precision, o.max_iters = precision, max_iters
+        o.tol_piv, o.tol_opt, o.tol_feas = tol_piv, tol_opt, tol_feas
+        o.k_deg, o.placement, o.block_threads = k_deg, placement, block_threads
+        o.stats = st.data_ptr() if st is not None else None
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        o.flags = (FLAG_SYNC if sync else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
+        m = np.ascontiguousarray(batch.m, np.int32)
+        n = np.ascontiguousarray(batch.n, np.int32)
+        _check(self.lib.lp_batch_solve_ex(
+            self.handle, N, _ptr(batch.A), _ptr(batch.b), _ptr(batch.c), _ptr(batch.sense),
+            m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+            _ptr(status), _ptr(x), _ptr(obj), ctypes.byref(o)))
+        return Solution(status, x, obj, st)
+
+    def kernel_times(self):
+        """[(name, ms)] of the kernels of the last solve made with time_kernels=True."""
+        cap = 16
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_float * cap)()
+        cnt = self.lib.lp_ctx_kernel_times(self.handle, names, ms, cap)
+        if cnt < 0:
+            raise LPBatchError(cnt, last_error())
+        return [(names[i].decode(), float(ms[i])) for i in range(min(cnt, cap))]
+
+
+def batch_solve(batch: DeviceBatch):
+    """lp_batch_solve: synchronous FP64 solve with the library's default context."""
+    import torch
+    lib = load()
+    dev = batch.A.device
+    N = batch.num_lps
+    status = torch.empty(N, dtype=torch.int32, device=dev)
+    x = torch.empty(int(batch.n.sum()), dtype=torch.float64, device=dev)
+    obj = torch.empty(N, dtype=torch.float64, device=dev)
+    m = np.ascontiguousarray(batch.m, np.int32)
+    n = np.ascontiguousarray(batch.n, np.int32)
+    torch.cuda.synchronize(dev)
+    _check(lib.lp_batch_solve(N, _ptr(batch.A), _ptr(batch.b), _ptr(batch.c), _ptr(batch.sense),
+                              m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+                              _ptr(status), _ptr(x), _ptr(obj)))
+    return Solution(status, x, obj, None)
