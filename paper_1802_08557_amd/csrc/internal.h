@@ -34,6 +34,8 @@ struct SolveArgs {
     char *scratch;            // HBM tableau slots, one per workgroup of the launch
     int64_t slot_bytes;
     int32_t *queue;           // work counter, zeroed before the launch
+    int32_t *defer_ids;       // wavefront kernel: LPs it could not take are appended here
+    int32_t *defer_count;     //   (the workgroup kernel then drains them)
     int32_t lds_bytes;        // dynamic LDS of each workgroup
     int32_t force_hbm;        // 1: never keep the tableau in LDS
     SolveParams prm;
@@ -44,6 +46,7 @@ struct SolveArgs {
 
 // Launchers (simplex_kernels.hip).  Return the hipError_t of the launch.
 hipError_t launch_zero_i32(int32_t *p, int count, hipStream_t s);
+hipError_t launch_set_i32(int32_t *p, int32_t value, hipStream_t s);
 hipError_t launch_simplex(bool fp32, int nt, const SolveArgs &a, int grid, hipStream_t s);
 // Workgroups of the simplex kernel that fit one CU with this LDS (occupancy query).
 int simplex_blocks_per_cu(bool fp32, int nt, int lds_bytes);
@@ -51,6 +54,13 @@ int simplex_blocks_per_cu(bool fp32, int nt, int lds_bytes);
 int64_t simplex_ctrl_bytes(bool fp32);
 // Allows every simplex kernel instantiation up to max_lds bytes of dynamic LDS.
 hipError_t simplex_configure(int max_lds);
+
+// One-wavefront-per-LP kernel (wave_kernels.hip) for LPs of at most 63
+// non-basic columns and 64*rb rows (rb = 1 or 2).
+hipError_t launch_simplex_wave(bool fp32, int rb, const SolveArgs &a, int grid, hipStream_t s);
+int simplex_wave_blocks_per_cu(bool fp32, int rb, int lds_bytes);
+int64_t wave_lds_aux_bytes(int rb, bool fp32);
+hipError_t simplex_wave_configure(int max_lds);
 
 // Size of the LDS control block + index arrays + pivot row/column buffers for an
 // LP with m rows and at most ncol_max non-basic columns, and the byte offset where

@@ -178,7 +178,8 @@ int lp_ctx_create(lp_ctx **out, int device)
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: device attribute query failed");
     }
-    if (lpb::simplex_configure(ctx->max_lds) != hipSuccess) {
+    if (lpb::simplex_configure(ctx->max_lds) != hipSuccess ||
+        lpb::simplex_wave_configure(ctx->max_lds) != hipSuccess) {
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: could not configure kernel LDS limits");
     }
@@ -248,23 +249,54 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     if (fp32) return fail(LP_ERR_ARG, "LP_PREC_FP32_CERT64 is not available in this build");
     hipStream_t stream = reinterpret_cast<hipStream_t>(opts.stream);
     DeviceGuard g(ctx->device);
+    const int64_t ts = fp32 ? 4 : 8;
+
+    // Kernel choice per LP: one wavefront for LPs of at most 63 columns and 128
+    // rows whose tableau fits LDS, a workgroup otherwise (or when the caller
+    // fixes the workgroup size or asks for HBM placement).
+    const bool auto_kernel = opts.block_threads == 0 && opts.placement != LP_PLACE_HBM;
+    auto wave_fit = [&](int64_t mk, int64_t nk) {
+        return nk <= 63 && mk <= 128 &&
+               lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, fp32) + mk * lpb::tableau_ld(int(nk) + 1) * ts <=
+                   ctx->max_lds;
+    };
+    std::vector<int32_t> wave_ids, block_ids;
+    int64_t n_wave = 0;
+    int wm_max = 0, wn_max = 0;
+    for (int64_t k = 0; k < num_lps; ++k) {
+        const bool w = auto_kernel && wave_fit(m[k], n[k]);
+        if (w) {
+            ++n_wave;
+            wm_max = std::max(wm_max, m[k]);
+            wn_max = std::max(wn_max, n[k]);
+        }
+        if (!uniform) (w ? wave_ids : block_ids).push_back(int32_t(k));
+    }
+    const int64_t n_block = num_lps - n_wave;
 
     lpb::SolveArgs a;
     std::memset(&a, 0, sizeof a);
-    a.num = num_lps;
     a.A = A; a.b = b; a.c = c; a.sense = sense;
     a.status = status; a.x = x; a.obj = obj;
     a.stats = opts.stats;
     a.prm = fill_params(opts, fp32);
+
+    // Device metadata: [m][n][aoff][roff][coff] (non-uniform only), then the
+    // wavefront id list and the deferred/workgroup id list (capacity num_lps).
+    const size_t sz_shape = uniform ? 0 : size_t(num_lps) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
+    const size_t sz_ids = size_t(num_lps) * sizeof(int32_t);
+    {
+        int rc = ctx->meta.ensure(sz_shape + 2 * sz_ids);
+        if (rc != LP_OK) return rc;
+    }
+    char *meta = static_cast<char *>(ctx->meta.p);
+    int32_t *d_wave_ids = reinterpret_cast<int32_t *>(meta + sz_shape);
+    int32_t *d_defer_ids = d_wave_ids + num_lps;
     if (uniform) {
         a.um = m0;
         a.un = n0;
     } else {
-        // Per-LP sizes and offsets to the device (small next to the batch itself).
-        const size_t bytes = size_t(num_lps) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
-        int rc = ctx->meta.ensure(bytes);
-        if (rc != LP_OK) return rc;
-        std::vector<char> host(bytes);
+        std::vector<char> host(sz_shape + sz_ids + size_t(n_block) * sizeof(int32_t));
         int32_t *hm = reinterpret_cast<int32_t *>(host.data());
         int32_t *hn = hm + num_lps;
         int64_t *ha = reinterpret_cast<int64_t *>(hn + num_lps);
@@ -275,18 +307,43 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             ha[k] = oa; hr[k] = orr; hc[k] = oc;
             oa += int64_t(m[k]) * n[k]; orr += m[k]; oc += n[k];
         }
-        HIP_TRY(hipMemcpyAsync(ctx->meta.p, host.data(), bytes, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipStreamSynchronize(stream));  // host buffer is about to go away
-        char *d = static_cast<char *>(ctx->meta.p);
-        a.m = reinterpret_cast<int32_t *>(d);
+        int32_t *hw = reinterpret_cast<int32_t *>(host.data() + sz_shape);
+        std::copy(wave_ids.begin(), wave_ids.end(), hw);
+        int32_t *hb = hw + num_lps;
+        std::copy(block_ids.begin(), block_ids.end(), hb);
+        HIP_TRY(hipMemcpyAsync(meta, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));  // the host staging buffer goes away
+        a.m = reinterpret_cast<int32_t *>(meta);
         a.n = a.m + num_lps;
         a.aoff = reinterpret_cast<int64_t *>(const_cast<int32_t *>(a.n + num_lps));
         a.roff = a.aoff + num_lps;
         a.coff = a.roff + num_lps;
     }
+    int32_t *cnt = static_cast<int32_t *>(ctx->counters.p);  // [0] wave queue, [1] block queue, [2] deferred
+    const bool timing = (opts.flags & LP_FLAG_TIME_KERNELS) != 0;
 
-    // Plan: workgroup size, LDS budget, resident workgroups, HBM slots.
-    const int64_t ts = fp32 ? 4 : 8;
+    if (n_wave > 0) {
+        const int rb = wm_max > 64 ? 2 : 1;
+        lpb::SolveArgs w = a;
+        w.num = n_wave;
+        w.ids = uniform ? nullptr : d_wave_ids;
+        w.queue = cnt;
+        w.defer_ids = d_defer_ids;
+        w.defer_count = cnt + 2;
+        const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) +
+                            int64_t(wm_max) * lpb::tableau_ld(wn_max + 1) * ts;
+        w.lds_bytes = int32_t(lds);
+        const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
+        if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
+        const int64_t grid = std::min<int64_t>(n_wave, int64_t(per_cu) * ctx->num_cu);
+        HIP_TRY(lpb::launch_zero_i32(cnt, 1, stream));
+        HIP_TRY(lpb::launch_set_i32(cnt + 2, int32_t(n_block), stream));
+        Timer t(ctx, timing, stream, fp32 ? "simplex_wave_fp32" : "simplex_wave_fp64");
+        HIP_TRY(lpb::launch_simplex_wave(fp32, rb, w, int(grid), stream));
+        t.done();
+    }
+
+    // Workgroup kernel: every LP not given to a wavefront, plus the deferred ones.
     const int ncol_worst = n_max + m_max;
     lpb::LdsLayout L = lpb::lds_layout(m_max, ncol_worst, ts, lpb::simplex_ctrl_bytes(fp32));
     // Tableau budget for the common case of no surplus columns (every row <= after
@@ -297,16 +354,16 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     int nt = opts.block_threads;
     if (!nt) nt = cells <= 64 * 64 ? 64 : (cells <= 256 * 256 ? 256 : 512);
     int64_t lds = L.tab;
-    bool want_lds = opts.placement != LP_PLACE_HBM && L.tab + tab_common <= ctx->max_lds;
+    const bool want_lds = opts.placement != LP_PLACE_HBM && L.tab + tab_common <= ctx->max_lds;
     if (want_lds) lds = L.tab + tab_common;
     if (lds > ctx->max_lds)
         return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index "
                     "arrays (device limit %d)", m_max, ncol_worst, (long long)lds, ctx->max_lds);
     a.lds_bytes = int32_t(lds);
     a.force_hbm = opts.placement == LP_PLACE_HBM;
-    int per_cu = lpb::simplex_blocks_per_cu(fp32, nt, int(lds));
+    const int per_cu = lpb::simplex_blocks_per_cu(fp32, nt, int(lds));
     if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for %d threads, %lld B LDS", nt, (long long)lds);
-    int64_t grid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
+    const int64_t grid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
     const bool need_hbm = !want_lds || tab_worst > tab_common;
     if (need_hbm) {
         a.slot_bytes = lpb::align16(tab_worst);
@@ -314,12 +371,18 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         if (rc != LP_OK) return rc;
         a.scratch = static_cast<char *>(ctx->scratch.p);
     }
-    a.queue = static_cast<int32_t *>(ctx->counters.p);
-
-    const bool timing = (opts.flags & LP_FLAG_TIME_KERNELS) != 0;
-    HIP_TRY(lpb::launch_zero_i32(a.queue, 1, stream));
+    a.queue = cnt + 1;
+    if (n_wave > 0) {
+        a.num = num_lps;  // upper bound; the deferred count is read on the device
+        a.ids = d_defer_ids;
+        a.num_dev = cnt + 2;
+    } else {
+        a.num = num_lps;
+        a.ids = nullptr;
+    }
+    HIP_TRY(lpb::launch_zero_i32(cnt + 1, 1, stream));
     {
-        Timer t(ctx, timing, stream, fp32 ? "simplex_fp32" : "simplex_fp64");
+        Timer t(ctx, timing, stream, fp32 ? "simplex_block_fp32" : "simplex_block_fp64");
         HIP_TRY(lpb::launch_simplex(fp32, nt, a, int(grid), stream));
         t.done();
     }

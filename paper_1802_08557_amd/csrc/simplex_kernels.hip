@@ -487,6 +487,11 @@ __global__ void zero_i32_kernel(int32_t *p, int count)
         p[i] = 0;
 }
 
+__global__ void set_i32_kernel(int32_t *p, int32_t value)
+{
+    if (threadIdx.x == 0) *p = value;
+}
+
 template <typename T, int NT>
 hipError_t launch_t(const SolveArgs &a, int grid, hipStream_t s)
 {
@@ -509,6 +514,12 @@ int occ_t(int lds)
 hipError_t launch_zero_i32(int32_t *p, int count, hipStream_t s)
 {
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_i32(int32_t *p, int32_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(64), 0, s, p, value);
     return hipGetLastError();
 }
 
