@@ -104,22 +104,23 @@ def main():
         ctx.solve(db, stats=True, stream=stream, out=out)
     torch.cuda.synchronize()
 
-    kern_ms = []
+    ctx.kernel_times()  # forget warm-up timings
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     start.record(stream)
     for _ in range(args.steps):
         ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True)
-        kern_ms.append(ctx.kernel_times())
     stop.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     total_ms = start.elapsed_time(stop)
     ms_per_step = total_ms / args.steps
 
-    names = [k for k, _ in kern_ms[0]]
-    per_kernel = {nm: float(np.mean([dict(ks)[nm] for ks in kern_ms])) for nm in names}
+    per_kernel = {}
+    for nm, v in ctx.kernel_times():
+        per_kernel.setdefault(nm, []).append(v)
+    per_kernel = {nm: float(np.mean(v)) for nm, v in per_kernel.items()}
     dom = max(per_kernel, key=per_kernel.get)
     stats = out.stats.cpu().numpy()
     status = out.status.cpu().numpy()

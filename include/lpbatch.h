@@ -153,11 +153,12 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
                       const lp_options *opts);
 
 /*
- * lp_ctx_kernel_times -- durations of the kernels of the context's last
- * lp_batch_solve_ex made with LP_FLAG_TIME_KERNELS, in launch order.
- * Synchronises on the recorded events.  Writes up to `cap` entries of
- * names[] (static strings) and ms[]; returns how many kernels there were, or
- * a negative LP_ERR_* code.
+ * lp_ctx_kernel_times -- durations of every kernel launched by the context's
+ * lp_batch_solve_ex calls made with LP_FLAG_TIME_KERNELS since the previous
+ * lp_ctx_kernel_times call, in launch order.  Synchronises on the recorded
+ * events, then forgets them.  Writes up to `cap` entries of names[] (static
+ * strings) and ms[]; returns how many kernels were recorded, or a negative
+ * LP_ERR_* code.
  */
 int lp_ctx_kernel_times(lp_ctx *ctx, const char **names, float *ms, int cap);
 

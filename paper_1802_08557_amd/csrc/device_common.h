@@ -52,6 +52,107 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// ---- DPP / permlane reductions (all 64 lanes must be active) ---------------
+// Lane patterns (checked on gfx950): quad_perm [1,0,3,2] and [2,3,0,1] swap
+// neighbours at distance 1 and 2, row_half_mirror reverses each group of 8,
+// row_mirror each row of 16; permlane16_swap(v, v) yields {even-row value,
+// odd-row value} and permlane32_swap(v, v) {low-half value, high-half value}
+// at the lane's own position.  After the six steps every lane holds the result.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+struct Pair32 { int a, b; };
+
+__device__ __forceinline__ Pair32 swap16(int v)
+{
+    auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return {int(p[0]), int(p[1])};
+}
+__device__ __forceinline__ Pair32 swap32(int v)
+{
+    auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return {int(p[0]), int(p[1])};
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+    v = min(v, dpp_i<0xB1>(v));
+    v = min(v, dpp_i<0x4E>(v));
+    v = min(v, dpp_i<0x141>(v));
+    v = min(v, dpp_i<0x140>(v));
+    Pair32 p = swap16(v);
+    v = min(p.a, p.b);
+    p = swap32(v);
+    return min(p.a, p.b);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v)
+{
+    return __hiloint2double(dpp_i<CTRL>(__double2hiint(v)), dpp_i<CTRL>(__double2loint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+
+__device__ __forceinline__ void swap16_f(double v, double &a, double &b)
+{
+    Pair32 lo = swap16(__double2loint(v)), hi = swap16(__double2hiint(v));
+    a = __hiloint2double(hi.a, lo.a);
+    b = __hiloint2double(hi.b, lo.b);
+}
+__device__ __forceinline__ void swap32_f(double v, double &a, double &b)
+{
+    Pair32 lo = swap32(__double2loint(v)), hi = swap32(__double2hiint(v));
+    a = __hiloint2double(hi.a, lo.a);
+    b = __hiloint2double(hi.b, lo.b);
+}
+__device__ __forceinline__ void swap16_f(float v, float &a, float &b)
+{
+    Pair32 p = swap16(__float_as_int(v));
+    a = __int_as_float(p.a);
+    b = __int_as_float(p.b);
+}
+__device__ __forceinline__ void swap32_f(float v, float &a, float &b)
+{
+    Pair32 p = swap32(__float_as_int(v));
+    a = __int_as_float(p.a);
+    b = __int_as_float(p.b);
+}
+
+// Exact minimum / maximum of a floating-point value over the wavefront (no NaN).
+template <typename T>
+__device__ __forceinline__ T wave_min_f(T v)
+{
+    v = fmin(v, dpp_f<0xB1>(v));
+    v = fmin(v, dpp_f<0x4E>(v));
+    v = fmin(v, dpp_f<0x141>(v));
+    v = fmin(v, dpp_f<0x140>(v));
+    T a, b;
+    swap16_f(v, a, b);
+    v = fmin(a, b);
+    swap32_f(v, a, b);
+    return fmin(a, b);
+}
+template <typename T>
+__device__ __forceinline__ T wave_max_f(T v)
+{
+    v = fmax(v, dpp_f<0xB1>(v));
+    v = fmax(v, dpp_f<0x4E>(v));
+    v = fmax(v, dpp_f<0x141>(v));
+    v = fmax(v, dpp_f<0x140>(v));
+    T a, b;
+    swap16_f(v, a, b);
+    v = fmax(a, b);
+    swap32_f(v, a, b);
+    return fmax(a, b);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane)
 {
     return (uint64_t(1) << lane) - 1;

@@ -220,8 +220,6 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         return fail(LP_ERR_ARG, "block_threads must be 0, 64, 128, 256 or 512");
     if (opts.placement < 0 || opts.placement > LP_PLACE_HBM)
         return fail(LP_ERR_ARG, "unknown placement %d", opts.placement);
-    ctx->times.clear();
-    ctx->events_used = 0;
     if (num_lps == 0) return LP_OK;
     if (!A || !b || !c || !sense || !m || !n || !status || !x || !obj)
         return fail(LP_ERR_ARG, "a batch pointer is NULL");
@@ -402,6 +400,8 @@ int lp_ctx_kernel_times(lp_ctx *ctx, const char **names, float *ms, int cap)
         if (names) names[i] = ctx->times[i].name;
         if (ms) ms[i] = v;
     }
+    ctx->times.clear();
+    ctx->events_used = 0;
     return cnt;
 }
 

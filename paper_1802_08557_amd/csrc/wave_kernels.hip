@@ -7,12 +7,14 @@
 //     a pivot, its pivot-row entry prow_j;
 //   * lane i (+64 r) owns row i: its basic variable, sign/sense flags and its
 //     pivot-column entry pcol_i;
-//   * the constraint rows live in LDS, row-major with an odd stride.
-// Step 1 is a wavefront argmin over the lanes' reduced costs; Step 2 reads the
-// entering column and the rhs column (one LDS element per lane) and reduces
-// the ratios; Step 3 sweeps the rows in groups of U -- U independent LDS
-// reads, U fma, U writes -- with the row's pivot-column entry read from its
-// owning lane (readlane), then rewrites the swapped column and the pivot row.
+//   * the constraint rows live in LDS, column-major (lane j's column is
+//     contiguous) with a column stride of an odd number of 16-byte units.
+// Step 1 is a wavefront DPP/permlane reduction over the lanes' reduced costs;
+// Step 2 reads the entering column and the rhs column (contiguous, one element
+// per lane) and reduces the ratios; Step 3 sweeps each lane's column in 16-byte
+// vectors, sixteen rows per group -- all reads, then the fma, then all writes --
+// with each row's pivot-column entry read from its owning lane (readlane),
+// then rewrites the swapped column and the pivot row.
 // The arithmetic of every element (fma(-pcol_i, prow_j, t_ij), prow_j =
 // t_lj / PE, Phase I and Phase II objective rows summed in row order) is the
 // same as in the workgroup kernel, so both give bitwise-identical results.
@@ -28,7 +30,18 @@
 namespace lpb {
 namespace {
 
-constexpr int U = 8;  // rows per sweep group
+// Column stride (in elements) of the column-major LDS tableau: the smallest
+// odd multiple of 16 bytes that holds m rows.  Lane j's column is contiguous,
+// so the row sweep moves 16 bytes per lane per access, and an odd number of
+// 16-byte units between neighbouring lanes' columns keeps those accesses free
+// of bank conflicts.
+template <typename T>
+__host__ __device__ constexpr int col_stride(int m)
+{
+    constexpr int R = 16 / int(sizeof(T));
+    const int u = (m + R - 1) / R;
+    return R * (u | 1);
+}
 
 // Uniform value of row i from a per-row register array (row i lives in lane i % 64
 // of block i / 64).
@@ -36,7 +49,7 @@ template <int RB, typename V>
 __device__ __forceinline__ V row_get(const V (&arr)[RB], int i)
 {
     if constexpr (RB == 1) {
-        return lane_get(arr[0], i);
+        return lane_get(arr[0], i & 63);
     } else {
         V out = lane_get(arr[0], i & 63);
 #pragma unroll
@@ -48,10 +61,10 @@ __device__ __forceinline__ V row_get(const V (&arr)[RB], int i)
 
 template <typename T, int RB>
 struct WaveLP {
-    int m, n, N, C, ld, nart;
+    int m, n, N, C, ldm, nart;
     int64_t k, ro, co;
     const double *A, *b, *c;
-    T *tab;
+    T *tab;  // column-major: element (i, j) at tab[j * ldm + i]
     int rowf[RB], basis[RB];
     T pcol[RB];
     int nonb;  // this lane's column
@@ -59,38 +72,62 @@ struct WaveLP {
     int iters, it1, degp, cap;
 };
 
+// Rows r0 .. r0+R-1 of one 16-byte vector of this lane's column:
+// v[r] = fma(-pcol_row, prow, v[r]).  Rows at or past m are padding that is
+// never read back, so whatever pivot-column entry they pick up is irrelevant.
+template <typename T, int RB, typename V>
+__device__ __forceinline__ void update_vec(V &v, int r0, const T (&pcol)[RB], T prow)
+{
+    constexpr int R = 16 / int(sizeof(T));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T f = row_get<RB>(pcol, r0 + r);
+        v[r] = fma(-f, prow, v[r]);
+    }
+}
+
 template <typename T, int RB>
 __device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
 {
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int R = 16 / int(sizeof(T));
+    constexpr int G = 16 / R;  // vectors per group of 16 rows
     const int lane = threadIdx.x;
-    const int m = P.m, C = P.C, ld = P.ld;
+    const int m = P.m, C = P.C, ldm = P.ldm;
     T *tab = P.tab;
     const T pe = row_get<RB>(P.pcol, l);
     T prow = T(0);
-    if (lane < C) prow = (lane == e) ? T(1) / pe : tab[l * ld + lane] / pe;
+    if (lane < C) prow = (lane == e) ? T(1) / pe : tab[lane * ldm + l] / pe;
     const T de = lane_get(P.d, e);
     if (lane < C) P.d = fma(-de, prow, (lane == e) ? T(0) : P.d);
-    // Sweep every row; the pivot row and the swapped column are rewritten after.
-    for (int i0 = 0; i0 < m; i0 += U) {
-        T v[U];
+    // Sweep this lane's column in 16-byte vectors, G vectors (16 rows) per
+    // group; the pivot row and the swapped column are rewritten afterwards.
+    if (lane < C) {
+        V *col = reinterpret_cast<V *>(tab + lane * ldm);
+        const int nv = (m + R - 1) / R;
+        int k0 = 0;
+        for (; k0 + G <= nv; k0 += G) {
+            V v[G];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (i0 + u < m && lane < C) v[u] = tab[(i0 + u) * ld + lane];
+            for (int g = 0; g < G; ++g) v[g] = col[k0 + g];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (i0 + u < m) {
-                const T f = row_get<RB>(P.pcol, i0 + u);
-                if (lane < C) tab[(i0 + u) * ld + lane] = fma(-f, prow, v[u]);
-            }
+            for (int g = 0; g < G; ++g) update_vec<T, RB>(v[g], (k0 + g) * R, P.pcol, prow);
+#pragma unroll
+            for (int g = 0; g < G; ++g) col[k0 + g] = v[g];
+        }
+        for (; k0 < nv; ++k0) {
+            V v = col[k0];
+            update_vec<T, RB>(v, k0 * R, P.pcol, prow);
+            col[k0] = v;
         }
     }
     const T pre = lane_get(prow, e);  // 1 / PE
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         const int i = lane + 64 * r;
-        if (i < m) tab[i * ld + e] = (i == l) ? pre : fma(-P.pcol[r], pre, T(0));
+        if (i < m) tab[e * ldm + i] = (i == l) ? pre : fma(-P.pcol[r], pre, T(0));
     }
-    if (lane < C) tab[l * ld + lane] = prow;
+    if (lane < C) tab[lane * ldm + l] = prow;
     const int bl = row_get<RB>(P.basis, l);
     const int ne = lane_get(P.nonb, e);
 #pragma unroll
@@ -108,16 +145,37 @@ __device__ __forceinline__ void load_pcol(WaveLP<T, RB> &P, int e)
     for (int r = 0; r < RB; ++r) {
         const int i = lane + 64 * r;
         T a = T(0);
-        if (i < P.m) a = P.tab[i * P.ld + e];
+        if (i < P.m) a = P.tab[e * P.ldm + i];
         P.pcol[r] = (P.rowf[r] & (kRowDead | kRowPad)) ? T(0) : a;
     }
+}
+
+// Step 1: the entering column (wavefront-uniform), or -1 when none is eligible.
+// Dantzig: the largest d_j, ties to the smallest Bland index; Bland: the
+// smallest eligible Bland index.
+template <typename T>
+__device__ __forceinline__ int price(bool elig, T d, int nonb, bool bland)
+{
+    const int lane = threadIdx.x;
+    const uint64_t any = __ballot(elig);
+    if (!any) return -1;
+    if (!bland) {
+        const T best = wave_max_f(elig ? d : -t_inf<T>());
+        const uint64_t tied = __ballot(elig && d == best);
+        if (__popcll(tied) == 1) return __builtin_ctzll(tied);
+        const bool in = (tied >> lane) & 1;
+        const int bmin = wave_min_i(in ? nonb : kBig);
+        return __builtin_ctzll(__ballot(in && nonb == bmin));
+    }
+    const int bmin = wave_min_i(elig ? nonb : kBig);
+    return __builtin_ctzll(__ballot(elig && nonb == bmin));
 }
 
 template <typename T, int RB>
 __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveParams &prm, int *enter)
 {
     const int lane = threadIdx.x;
-    const int m = P.m, N = P.N, ld = P.ld, nm = P.n + P.m;
+    const int m = P.m, N = P.N, ldm = P.ldm, nm = P.n + P.m;
     const T tol_piv = T(prm.tol_piv);
     T *tab = P.tab;
     int deg_run = 0;
@@ -125,35 +183,38 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
         if (P.iters >= P.cap) return kIterLimit;
         const bool bland = prm.k_deg > 0 && deg_run >= prm.k_deg;
         // Step 1.
-        T k1 = t_inf<T>();
-        int k2 = kBig, p = -1;
-        if (lane < N && P.d > eps_opt && P.nonb < nm) {
-            k1 = bland ? T(0) : -P.d;
-            k2 = P.nonb;
-            p = lane;
-        }
-        wave_argmin(k1, k2, p);
-        const int e = uniform(p);
+        const int e = price<T>(lane < N && P.d > eps_opt && P.nonb < nm, P.d, P.nonb, bland);
         if (e < 0) return kOptimal;
-        // Step 2.
-        k1 = t_inf<T>(); k2 = kBig; p = -1;
+        // Step 2: each lane's best row (ties to the smaller basic index), then
+        // the wavefront minimum ratio, ties to the smallest basic index.
+        T th_loc = t_inf<T>();
+        int bb_loc = kBig, row_loc = -1;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int i = lane + 64 * r;
             const bool live = !(P.rowf[r] & (kRowDead | kRowPad));
             T a = T(0), bi = T(0);
-            if (i < m) { a = tab[i * ld + e]; bi = tab[i * ld + N]; }
+            if (i < m) { a = tab[e * ldm + i]; bi = tab[N * ldm + i]; }
             P.pcol[r] = live ? a : T(0);
             if (live && a > tol_piv) {
                 const T th = (bi > T(0) ? bi : T(0)) / a;
                 const int bb = P.basis[r];
-                if (th < k1 || (th == k1 && bb < k2)) { k1 = th; k2 = bb; p = i; }
+                if (th < th_loc || (th == th_loc && bb < bb_loc)) { th_loc = th; bb_loc = bb; row_loc = i; }
             }
         }
-        wave_argmin(k1, k2, p);
-        const int l = uniform(p);
-        if (l < 0) { *enter = lane_get(P.nonb, e); return kUnbounded; }
-        if (k1 == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
+        if (!__ballot(row_loc >= 0)) { *enter = lane_get(P.nonb, e); return kUnbounded; }
+        const T best = wave_min_f(th_loc);
+        const uint64_t tied = __ballot(row_loc >= 0 && th_loc == best);
+        int src;
+        if (__popcll(tied) == 1) {
+            src = __builtin_ctzll(tied);
+        } else {
+            const bool in = (tied >> lane) & 1;
+            const int bmin = wave_min_i(in ? bb_loc : kBig);
+            src = __builtin_ctzll(__ballot(in && bb_loc == bmin));
+        }
+        const int l = lane_get(row_loc, src);
+        if (lane_get(th_loc, src) == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
         pivot<T, RB>(P, l, e);
         ++P.iters;
     }
@@ -232,9 +293,9 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
         }
         P.N = n + ng;
         P.C = P.N + 1;
-        P.ld = tableau_ld(P.C);
+        P.ldm = col_stride<T>(m);
         P.nart = nart;
-        const int64_t need = aux + int64_t(m) * P.ld * int64_t(sizeof(T));
+        const int64_t need = aux + int64_t(P.C) * P.ldm * int64_t(sizeof(T));
         if (P.C > 64 || m > 64 * RB || need > a.lds_bytes) {
             if (lane == 0) {
                 const int slot = atomicAdd(a.defer_count, 1);
@@ -243,7 +304,7 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
             item = lane_get(nxt, 0);
             continue;
         }
-        const int N = P.N, C = P.C, ld = P.ld;
+        const int N = P.N, C = P.C, ldm = P.ldm;
         T *tab = reinterpret_cast<T *>(smem + aux);
         P.tab = tab;
 
@@ -262,27 +323,48 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
             const int i = lane + 64 * r;
             P.basis[r] = (((P.rowf[r] >> 1) & 3) == kLE) ? n + i : n + m + i;
         }
-        for (int i0 = 0; i0 < m; i0 += U) {
-            double av[U];
+        {
+            // A (m x n, contiguous) copied with UB independent loads per lane in
+            // flight; row = (f + 0.5) / n in float is exact for f < 2^13.
+            constexpr int UB = 16;
+            const int mn = m * n;
+            const float inv_n = 1.0f / float(n);
+            for (int f0 = 0; f0 < mn; f0 += 64 * UB) {
+                double av[UB];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                av[u] = (i0 + u < m && lane < n) ? P.A[int64_t(i0 + u) * n + lane] : 0.0;
+                for (int u = 0; u < UB; ++u) {
+                    const int f = f0 + 64 * u + lane;
+                    av[u] = (f < mn) ? P.A[f] : 0.0;
+                }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u;
-                if (i < m) {
-                    const int f = row_get<RB>(P.rowf, i);
-                    const double sg = (f & kRowNeg) ? -1.0 : 1.0;
-                    double v;
-                    if (lane < n) {
+                for (int u = 0; u < UB; ++u) {
+                    const int f = f0 + 64 * u + lane;
+                    if (f < mn) {
+                        const int i = int((float(f) + 0.5f) * inv_n);
+                        const int j = f - i * n;
                         bad |= !isfinite(av[u]);
-                        v = sg * av[u];
-                    } else if (lane < N) {
-                        v = (lane == row_get<RB>(sc, i)) ? -1.0 : 0.0;
-                    } else {
-                        v = sg * row_get<RB>(bv, i);
+                        tab[j * ldm + i] = T(av[u]);
                     }
-                    if (lane < C) tab[i * ld + lane] = T(v);
+                }
+            }
+            // Rows with b < 0 are negated (sign normalisation).
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                uint64_t neg = __ballot(lane + 64 * r < m && (P.rowf[r] & kRowNeg));
+                while (neg) {
+                    const int i = 64 * r + __builtin_ctzll(neg);
+                    neg &= neg - 1;
+                    if (lane < n) tab[lane * ldm + i] = -tab[lane * ldm + i];
+                }
+            }
+            // Surplus columns and the right-hand side, one row per lane.
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int i = lane + 64 * r;
+                if (i < m) {
+                    const double sg = (P.rowf[r] & kRowNeg) ? -1.0 : 1.0;
+                    for (int g = 0; g < ng; ++g) tab[(n + g) * ldm + i] = (sc[r] == n + g) ? T(-1) : T(0);
+                    tab[N * ldm + i] = T(sg * bv[r]);
                 }
             }
         }
@@ -305,7 +387,7 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
                 T acc = T(0);
                 for (int i = 0; i < m; ++i) {
                     const int sen = (row_get<RB>(P.rowf, i) >> 1) & 3;
-                    if (sen != kLE && lane < C) acc += tab[i * ld + lane];
+                    if (sen != kLE && lane < C) acc += tab[lane * ldm + i];
                 }
                 P.d = acc;
                 const double dmax = wave_max(lane < N ? fabs(double(acc)) : 0.0);
@@ -329,14 +411,9 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
                             const int bit = __builtin_ctzll(am);
                             am &= am - 1;
                             const int i = 64 * r + bit;
-                            T k1 = T(0);
-                            int k2 = kBig, p = -1;
-                            if (lane < N && P.nonb < n + m) {
-                                const T v = tab[i * ld + lane];
-                                if (fabs(v) > tol_piv) { k2 = P.nonb; p = lane; }
-                            }
-                            wave_argmin(k1, k2, p);
-                            const int e = uniform(p);
+                            bool ok = false;
+                            if (lane < N && P.nonb < n + m) ok = fabs(tab[lane * ldm + i]) > tol_piv;
+                            const int e = price<T>(ok, T(0), P.nonb, true);
                             if (e >= 0) {
                                 load_pcol<T, RB>(P, e);
                                 pivot<T, RB>(P, i, e);
@@ -365,7 +442,7 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
                         const int bit = __builtin_ctzll(mk);
                         mk &= mk - 1;
                         const T f = lane_get(cb[r], bit);
-                        if (lane < C) acc = fma(-f, tab[(64 * r + bit) * ld + lane], acc);
+                        if (lane < C) acc = fma(-f, tab[lane * ldm + 64 * r + bit], acc);
                     }
                 }
                 P.d = acc;
@@ -380,7 +457,7 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
             for (int r = 0; r < RB; ++r) {
                 const int i = lane + 64 * r;
                 const int bvr = P.basis[r];
-                if (i < m && bvr < n && !(P.rowf[r] & kRowDead)) xv[bvr] = tab[i * ld + N];
+                if (i < m && bvr < n && !(P.rowf[r] & kRowDead)) xv[bvr] = tab[N * ldm + i];
             }
         }
         const double xj = (lane < n) ? double(xv[lane]) : 0.0;

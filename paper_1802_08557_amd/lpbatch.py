@@ -175,9 +175,9 @@ class Context:
             _ptr(status), _ptr(x), _ptr(obj), ctypes.byref(o)))
         return Solution(status, x, obj, st)
 
-    def kernel_times(self):
-        """[(name, ms)] of the kernels of the last solve made with time_kernels=True."""
-        cap = 16
+    def kernel_times(self, cap=4096):
+        """[(name, ms)] of every kernel of the solves made with time_kernels=True
+        since the previous call (the context then forgets them)."""
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_float * cap)()
         cnt = self.lib.lp_ctx_kernel_times(self.handle, names, ms, cap)
