@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lpbatch.h"
+#include "lpbatch.h"
 #include "internal.h"
 
 namespace {

@@ -13,8 +13,8 @@
 // Step 2 reads the entering column and the rhs column (contiguous, one element
 // per lane) and reduces the ratios; Step 3 sweeps each lane's column in 16-byte
 // vectors, sixteen rows per group -- all reads, then the fma, then all writes --
-// with each row's pivot-column entry read from its owning lane (readlane),
-// then rewrites the swapped column and the pivot row.
+// with the rows' pivot-column entries broadcast from column e in LDS, then
+// rewrites the swapped column and the pivot row.
 // The arithmetic of every element (fma(-pcol_i, prow_j, t_ij), prow_j =
 // t_lj / PE, Phase I and Phase II objective rows summed in row order) is the
 // same as in the workgroup kernel, so both give bitwise-identical results.
@@ -72,18 +72,14 @@ struct WaveLP {
     int iters, it1, degp, cap;
 };
 
-// Rows r0 .. r0+R-1 of one 16-byte vector of this lane's column:
-// v[r] = fma(-pcol_row, prow, v[r]).  Rows at or past m are padding that is
-// never read back, so whatever pivot-column entry they pick up is irrelevant.
-template <typename T, int RB, typename V>
-__device__ __forceinline__ void update_vec(V &v, int r0, const T (&pcol)[RB], T prow)
+// Rows of one 16-byte vector of this lane's column: v[r] = fma(-w[r], prow,
+// v[r]) with w the same rows of the pivot column.
+template <typename T, typename V>
+__device__ __forceinline__ void update_vec(V &v, const V &w, T prow)
 {
     constexpr int R = 16 / int(sizeof(T));
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const T f = row_get<RB>(pcol, r0 + r);
-        v[r] = fma(-f, prow, v[r]);
-    }
+    for (int r = 0; r < R; ++r) v[r] = fma(-w[r], prow, v[r]);
 }
 
 template <typename T, int RB>
@@ -101,23 +97,33 @@ __device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
     const T de = lane_get(P.d, e);
     if (lane < C) P.d = fma(-de, prow, (lane == e) ? T(0) : P.d);
     // Sweep this lane's column in 16-byte vectors, G vectors (16 rows) per
-    // group; the pivot row and the swapped column are rewritten afterwards.
+    // group.  The same rows of the pivot column are read from column e by
+    // every lane (one broadcast address per load); lane e rewrites column e
+    // in the same sweep, but only rows whose pivot-column values every lane
+    // has already read, since a wavefront's LDS accesses complete in program
+    // order.  The pivot row and the swapped column are rewritten afterwards;
+    // padding rows past m take whatever values and are never read back.
     if (lane < C) {
         V *col = reinterpret_cast<V *>(tab + lane * ldm);
+        const V *pc = reinterpret_cast<const V *>(tab + e * ldm);
         const int nv = (m + R - 1) / R;
         int k0 = 0;
         for (; k0 + G <= nv; k0 += G) {
-            V v[G];
+            V v[G], w[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) v[g] = col[k0 + g];
+            for (int g = 0; g < G; ++g) {
+                v[g] = col[k0 + g];
+                w[g] = pc[k0 + g];
+            }
 #pragma unroll
-            for (int g = 0; g < G; ++g) update_vec<T, RB>(v[g], (k0 + g) * R, P.pcol, prow);
+            for (int g = 0; g < G; ++g) update_vec<T, V>(v[g], w[g], prow);
 #pragma unroll
             for (int g = 0; g < G; ++g) col[k0 + g] = v[g];
         }
         for (; k0 < nv; ++k0) {
             V v = col[k0];
-            update_vec<T, RB>(v, k0 * R, P.pcol, prow);
+            const V w = pc[k0];
+            update_vec<T, V>(v, w, prow);
             col[k0] = v;
         }
     }
@@ -220,40 +226,97 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
     }
 }
 
-// Bytes of LDS the wave kernel keeps in front of the tableau.
+// Bytes of LDS the wave kernel keeps in front of the tableau: the surplus
+// column -> row map, the x staging vector and the LP's objective c.
 __host__ __device__ constexpr int64_t wave_aux_bytes(int rb, int64_t tsize)
 {
-    return align16(4 * 64 * rb) + align16(tsize * 64);
+    return align16(4 * 64 * rb) + align16(tsize * 64) + 8 * 64;
+}
+
+// Doubles of A each lane prefetches: LPs with m * n <= 64 * NPF have their
+// whole constraint matrix loaded into registers one LP ahead.
+constexpr int NPF = 40;
+
+// An LP's geometry and input data, loaded into registers ahead of its solve.
+template <int RB>
+struct Fetch {
+    int64_t k, ro, co;
+    int m, n;
+    const double *A;
+    bool has_a;
+    double av[NPF];  // A in flat row-major order, element lane + 64 t
+    double bv[RB];   // b of row lane + 64 r
+    int sv[RB];      // sense of row lane + 64 r
+    double cv;       // c of column lane
+};
+
+// Issues the loads of work item `item` (nothing waits for them here).
+template <int RB>
+__device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB> &F)
+{
+    const int lane = threadIdx.x;
+    const int64_t k = a.ids ? int64_t(a.ids[item]) : item;
+    F.k = k;
+    if (a.um > 0) {
+        F.m = a.um; F.n = a.un;
+        F.A = a.A + k * int64_t(a.um) * a.un;
+        F.ro = k * a.um;
+        F.co = k * a.un;
+    } else {
+        F.m = a.m[k]; F.n = a.n[k];
+        F.A = a.A + a.aoff[k];
+        F.ro = a.roff[k];
+        F.co = a.coff[k];
+    }
+    const int m = F.m, n = F.n;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int i = lane + 64 * r;
+        F.bv[r] = (i < m) ? a.b[F.ro + i] : 0.0;
+        F.sv[r] = (i < m) ? int(a.sense[F.ro + i]) : 0;
+    }
+    F.cv = (lane < n) ? a.c[F.co + lane] : 0.0;
+    const int mn = m * n;
+    F.has_a = mn <= 64 * NPF;
+    if (F.has_a) {
+        // One buffer descriptor over this LP's A: the hardware range check
+        // (offset < m*n*8) returns 0 past the end instead of reading further.
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double *>(F.A), short(0), mn * int(sizeof(double)), 0x00020000);
+#pragma unroll
+        for (int t = 0; t < NPF; ++t)
+            F.av[t] = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * t) * 8, 0, 0));
+    }
 }
 
 template <typename T, int RB>
-__global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void simplex_wave_kernel(SolveArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x;
     int *colrow = reinterpret_cast<int *>(smem);
     T *xv = reinterpret_cast<T *>(smem + align16(4 * 64 * RB));
+    double *cl = reinterpret_cast<double *>(smem + align16(4 * 64 * RB) + align16(sizeof(T) * 64));
     const int64_t aux = wave_aux_bytes(RB, sizeof(T));
-    int64_t item = blockIdx.x;
-    while (item < a.num) {
-        int nxt = 0;
-        if (lane == 0) nxt = int(gridDim.x) + atomicAdd(a.queue, 1);
-        const int64_t k = a.ids ? int64_t(a.ids[item]) : item;
+    const int64_t total = a.num_dev ? int64_t(*a.num_dev) : a.num;
+    // Work items: blockIdx.x and blockIdx.x + G first, then 2G + the queue
+    // counter; the next item is always known one LP ahead, so its data can be
+    // in flight while the current LP pivots.
+    const int64_t G = gridDim.x;
+    int64_t cur = blockIdx.x, nxt = blockIdx.x + G;
+    Fetch<RB> F;
+    if (cur < total) fetch<RB>(a, cur, F);
+    while (cur < total) {
+        int pend = 0;
+        if (lane == 0) pend = int(2 * G) + atomicAdd(a.queue, 1);
+        const int64_t k = F.k;
         WaveLP<T, RB> P;
         P.k = k;
-        if (a.um > 0) {
-            P.m = a.um; P.n = a.un;
-            P.A = a.A + k * int64_t(a.um) * a.un;
-            P.ro = k * a.um;
-            P.co = k * a.un;
-        } else {
-            P.m = a.m[k]; P.n = a.n[k];
-            P.A = a.A + a.aoff[k];
-            P.ro = a.roff[k];
-            P.co = a.coff[k];
-        }
-        P.b = a.b + P.ro;
-        P.c = a.c + P.co;
+        P.m = F.m; P.n = F.n;
+        P.A = F.A;
+        P.ro = F.ro;
+        P.co = F.co;
         const int m = P.m, n = P.n;
 
         // A1: sign-normalise and classify rows; surplus columns by ballot.
@@ -265,10 +328,9 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
         for (int r = 0; r < RB; ++r) {
             const int i = lane + 64 * r;
             int f = kRowPad;
-            double bi = 0.0;
+            const double bi = F.bv[r];
             if (i < m) {
-                bi = P.b[i];
-                const int s = a.sense[P.ro + i];
+                const int s = F.sv[r];
                 bad |= !isfinite(bi) || s < kLE || s > kEQ;
                 const bool neg = bi < 0.0;
                 int sen = (s < kLE || s > kEQ) ? kLE : s;
@@ -296,25 +358,23 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
         P.ldm = col_stride<T>(m);
         P.nart = nart;
         const int64_t need = aux + int64_t(P.C) * P.ldm * int64_t(sizeof(T));
-        if (P.C > 64 || m > 64 * RB || need > a.lds_bytes) {
-            if (lane == 0) {
-                const int slot = atomicAdd(a.defer_count, 1);
-                a.defer_ids[slot] = int32_t(k);
-            }
-            item = lane_get(nxt, 0);
-            continue;
+        const bool fits = P.C <= 64 && m <= 64 * RB && need <= a.lds_bytes;
+        if (!fits && lane == 0) {
+            const int slot = atomicAdd(a.defer_count, 1);
+            a.defer_ids[slot] = int32_t(k);
         }
         const int N = P.N, C = P.C, ldm = P.ldm;
         T *tab = reinterpret_cast<T *>(smem + aux);
         P.tab = tab;
 
-        // A2: index arrays and the tableau rows (U rows of A in flight).
+        // A2: index arrays and the tableau (column-major in LDS).
         P.nonb = kBig;
-        double cj = 0.0;
+        const double cj = F.cv;
+        if (fits) {
         if (lane < n) {
             P.nonb = lane;
-            cj = P.c[lane];
             bad |= !isfinite(cj);
+            cl[lane] = cj;
         } else if (lane < N) {
             P.nonb = n + colrow[lane - n];
         }
@@ -324,26 +384,42 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
             P.basis[r] = (((P.rowf[r] >> 1) & 3) == kLE) ? n + i : n + m + i;
         }
         {
-            // A (m x n, contiguous) copied with UB independent loads per lane in
-            // flight; row = (f + 0.5) / n in float is exact for f < 2^13.
-            constexpr int UB = 16;
+            // A scattered from flat row-major order into the columns.  Element
+            // f = lane + 64 t sits at row f / n, column f % n; stepping t by one
+            // advances the column by 64 % n and the row by 64 / n, plus one
+            // when the column wraps.
             const int mn = m * n;
-            const float inv_n = 1.0f / float(n);
-            for (int f0 = 0; f0 < mn; f0 += 64 * UB) {
-                double av[UB];
+            const int dq = 64 / n, dr = 64 - dq * n;
+            int ri = lane / n, cj2 = lane - (lane / n) * n;
+            if (F.has_a) {
 #pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    const int f = f0 + 64 * u + lane;
-                    av[u] = (f < mn) ? P.A[f] : 0.0;
+                for (int t = 0; t < NPF; ++t) {
+                    if (lane + 64 * t < mn) {
+                        bad |= !isfinite(F.av[t]);
+                        tab[cj2 * ldm + ri] = T(F.av[t]);
+                    }
+                    ri += dq;
+                    cj2 += dr;
+                    if (cj2 >= n) { cj2 -= n; ++ri; }
                 }
+            } else {
+                constexpr int UB = 16;
+                for (int f0 = 0; f0 < mn; f0 += 64 * UB) {
+                    double av[UB];
 #pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    const int f = f0 + 64 * u + lane;
-                    if (f < mn) {
-                        const int i = int((float(f) + 0.5f) * inv_n);
-                        const int j = f - i * n;
-                        bad |= !isfinite(av[u]);
-                        tab[j * ldm + i] = T(av[u]);
+                    for (int u = 0; u < UB; ++u) {
+                        const int f = f0 + 64 * u + lane;
+                        av[u] = (f < mn) ? P.A[f] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < UB; ++u) {
+                        if (f0 + 64 * u + lane < mn) {
+                            bad |= !isfinite(av[u]);
+                            tab[cj2 * ldm + ri] = T(av[u]);
+                        }
+                        ri += dq;
+                        cj2 += dr;
+                        if (cj2 >= n) { cj2 -= n; ++ri; }
                     }
                 }
             }
@@ -367,6 +443,14 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
                     tab[N * ldm + i] = T(sg * bv[r]);
                 }
             }
+        }
+        }  // fits
+        // The registers of F are free again: start loading the next LP.
+        if (nxt < total) fetch<RB>(a, nxt, F);
+        if (!fits) {
+            cur = nxt;
+            nxt = lane_get(pend, 0);
+            continue;
         }
         const bool invalid = __ballot(bad) != 0;
         const double cnorm = wave_max(fabs(cj));
@@ -431,10 +515,10 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     const int bvr = P.basis[r];
-                    cb[r] = (!(P.rowf[r] & (kRowDead | kRowPad)) && bvr < n) ? T(P.c[bvr]) : T(0);
+                    cb[r] = (!(P.rowf[r] & (kRowDead | kRowPad)) && bvr < n) ? T(cl[bvr]) : T(0);
                     nz[r] = __ballot(cb[r] != T(0));
                 }
-                T acc = (lane < N && P.nonb < n) ? T(P.c[P.nonb]) : T(0);
+                T acc = (lane < N && P.nonb < n) ? T(cl[P.nonb]) : T(0);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     uint64_t mk = nz[r];
@@ -495,7 +579,8 @@ __global__ __launch_bounds__(64) void simplex_wave_kernel(SolveArgs a)
                 if (i < m) a.basis_out[P.ro + i] = (P.rowf[r] & kRowDead) ? -1 : P.basis[r];
             }
         }
-        item = lane_get(nxt, 0);
+        cur = nxt;
+        nxt = lane_get(pend, 0);
     }
 }
 
