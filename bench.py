@@ -74,6 +74,52 @@ def cpu_baseline(batch, max_lps=100_000):
                             f"{threads} threads, {dt:.2f} s wall")
 
 
+KERNEL_SOURCES = ("paper_1802_08557_amd/csrc/wave_kernels.hip",
+                  "paper_1802_08557_amd/csrc/simplex_kernels.hip",
+                  "paper_1802_08557_amd/csrc/device_common.h",
+                  "paper_1802_08557_amd/csrc/internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (profiles/traffic.json), scaled
+    by the factors the same counters read for a copy of known size; None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(f"{kernel}@{workload}")
+    if not ent:
+        return None
+    return ent["fetch_bytes"] + ent["write_bytes"]
+
+
+def copy_calibration(gib):
+    """An elementwise copy kernel of a known size (dst = src * 1), for
+    calibrating FETCH_SIZE and WRITE_SIZE under rocprofv3: each launch reads and
+    writes gib GiB."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=n * 8, repeats=3)), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +128,11 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run a device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(LPs are independent, so several GPUs would each run their own share).",
@@ -135,6 +185,7 @@ def main():
         roof = dict(bound="hbm", achieved=(tab_bytes + hbm_bytes) / dom_s / 1e9,
                     peak=PEAK_HBM / 1e9, unit="GB/s",
                     frac=(tab_bytes + hbm_bytes) / dom_s / PEAK_HBM, traffic=None)
+    roof["traffic"] = measured_traffic(dom, batch.name)
     roof.update(kernel=dom, kernel_ms=per_kernel[dom], hbm_bytes_alg=hbm_bytes,
                 hbm_frac=hbm_bytes / dom_s / PEAK_HBM, tableau_bytes_alg=tab_bytes,
                 mean_pivots=mean_piv)

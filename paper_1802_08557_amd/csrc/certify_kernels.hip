@@ -1,0 +1,473 @@
+// certify_kernels.hip -- FP64 re-solve and certificate of a final basis.
+//
+// After a solve on a single-precision tableau, every LP's final basis is taken
+// back to the FP64 input data:
+//   * T = rows whose slack/surplus (or artificial) is non-basic ("tight"),
+//     S = basic structural variables; |T| = |S| = k for a square basis.
+//   * B_TS = the k x k block of the sign-normalised constraint matrix is
+//     LU-factorised with partial pivoting;  x_S = B_TS^-1 b_T  (x_B = B^-1 b),
+//     y_T = B_TS^-T c_S  (the duals, y = 0 on the other rows).
+//   * Primal certificate: x_S >= -tol and every non-tight row's slack or
+//     surplus >= -tol (a dropped redundant row's residual within tol).
+//   * Dual certificate (reduced costs): c_j - y^T a_j <= tol for every
+//     non-basic structural j, and for the logical of every tight row:
+//     -y_i <= tol (slack, <= row) or y_i <= tol (surplus, >= row).
+//     Together these give c^T x = b^T y, i.e. optimality (strong duality).
+//   * For an LP reported unbounded with entering variable q: the basis must
+//     pass the primal certificate and the ray (x_q = t, x_S = x_S - t B^-1 a_q)
+//     must keep every basic variable non-negative and raise the objective.
+// An LP whose result passes is written with its FP64 x and objective; any
+// other LP (failed certificate, singular block, or a status other than
+// optimal / unbounded / invalid input) is appended to the fallback list and
+// re-solved from scratch on the FP64 tableau.
+#include <math.h>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace lpb {
+namespace {
+
+constexpr int kTight = 32, kDeadRow = 64;
+
+template <int NT>
+struct CertCtrl {
+    int k, kt, fail, next;
+    int piv;
+    int pad[3];
+    double bnorm, cnorm, amax;
+    double rd[16];
+    int ri[16];
+};
+
+template <int NT>
+__device__ __forceinline__ double blk_max(double v, CertCtrl<NT> *sh)
+{
+    v = wave_max(v);
+    if constexpr (NT > 64) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) sh->rd[w] = v;
+        __syncthreads();
+        v = sh->rd[0];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) v = fmax(v, sh->rd[q]);
+        __syncthreads();
+    }
+    return v;
+}
+
+// Largest key over the block, ties to the smallest index (key >= 0, idx unique).
+template <int NT>
+__device__ __forceinline__ void blk_argmax(double &key, int &idx, CertCtrl<NT> *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ok = __shfl_xor(key, off);
+        const int oi = __shfl_xor(idx, off);
+        if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+    }
+    if constexpr (NT > 64) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) { sh->rd[w] = key; sh->ri[w] = idx; }
+        __syncthreads();
+        key = sh->rd[0]; idx = sh->ri[0];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) {
+            const double ok = sh->rd[q];
+            const int oi = sh->ri[q];
+            if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+        }
+        __syncthreads();
+    }
+}
+
+// Compacts the flagged entries of [0, count) into list (ascending); wave 0 only.
+__device__ __forceinline__ int compact(const int *flag, int mask, int count, int *list, int *pos)
+{
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    for (int i0 = 0; i0 < count; i0 += 64) {
+        const int i = i0 + lane;
+        const bool on = i < count && (flag[i] & mask);
+        const uint64_t b = __ballot(on);
+        if (on) {
+            const int p = base + __popcll(b & lanemask_lt(lane));
+            list[p] = i;
+            pos[i] = p;
+        } else if (i < count) {
+            pos[i] = -1;
+        }
+        base += __popcll(b);
+    }
+    return base;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    CertCtrl<NT> *sh = reinterpret_cast<CertCtrl<NT> *>(smem);
+    const int64_t total = a.num;
+    int64_t item = blockIdx.x;
+    while (item < total) {
+        if (tid == 0) sh->next = int(gridDim.x) + atomicAdd(a.queue, 1);
+        const int64_t k = item;
+        int m, n;
+        int64_t ao, ro, co;
+        if (a.um > 0) {
+            m = a.um; n = a.un; ao = k * int64_t(m) * n; ro = k * m; co = k * n;
+        } else {
+            m = a.m[k]; n = a.n[k]; ao = a.aoff[k]; ro = a.roff[k]; co = a.coff[k];
+        }
+        const double *A = a.A + ao, *b = a.b + ro, *c = a.c + co;
+        const int8_t *sense = a.sense + ro;
+        const int32_t *basis = a.basis + ro;
+        double *x = a.x + co;
+        const int st0 = a.status[k];
+        // LDS carve-up for this LP.
+        int *rowf = reinterpret_cast<int *>(smem + align16(sizeof(CertCtrl<NT>)));
+        int *tpos = rowf + m;
+        int *tlist = tpos + m;
+        int *colf = tlist + m;
+        int *spos = colf + n;
+        int *slist = spos + n;
+        double *vec = reinterpret_cast<double *>(smem + align16(sizeof(CertCtrl<NT>)) +
+                                                 align16(4 * int64_t(3 * m + 3 * n)));
+        const int kmax = min(m, n);
+        double *xs = vec;           // [kmax] x_S, then scratch
+        double *yt = xs + kmax;     // [kmax] y_T
+        double *wv = yt + kmax;     // [kmax] ray direction
+        int *perm = reinterpret_cast<int *>(wv + kmax);  // [kmax] row permutation of the LU
+        const int64_t mat_off = align16(sizeof(CertCtrl<NT>)) + align16(4 * int64_t(3 * m + 3 * n)) +
+                                align16(8 * 3 * int64_t(kmax) + 4 * int64_t(kmax));
+        int cert = 0;
+        bool fallback = !(st0 == kOptimal || st0 == kUnbounded);
+        if (st0 == kInvalid) fallback = false;
+        const bool work = st0 == kOptimal || st0 == kUnbounded;
+
+        if (work) {
+            // Rows: sign normalisation, and which rows are tight.
+            if (tid == 0) sh->fail = 0;
+            for (int i = tid; i < m; i += NT) {
+                const double bi = b[i];
+                int sen = sense[i];
+                const bool neg = bi < 0.0;
+                if (neg && sen != kEQ) sen = (sen == kLE) ? kGE : kLE;
+                rowf[i] = (neg ? kRowNeg : 0) | (sen << 1) | kTight;
+            }
+            for (int j = tid; j < n; j += NT) colf[j] = 0;
+            __syncthreads();
+            for (int r = tid; r < m; r += NT) {
+                const int v = basis[r];
+                if (v < -1 || v >= n + 2 * m) {
+                    sh->fail = 9;  // not a basis of this LP
+                } else if (v < 0) {
+                    atomicOr(&rowf[r], kDeadRow);
+                    atomicAnd(&rowf[r], ~kTight);
+                } else if (v < n) {
+                    colf[v] = kTight;
+                } else if (v < n + m) {
+                    atomicAnd(&rowf[v - n], ~kTight);
+                } else {
+                    atomicOr(&rowf[v - n - m], kDeadRow);
+                    atomicAnd(&rowf[v - n - m], ~kTight);
+                }
+            }
+            __syncthreads();
+            if (wave == 0) {
+                const int kt = compact(rowf, kTight, m, tlist, tpos);
+                const int ks = compact(colf, kTight, n, slist, spos);
+                if (lane == 0) { sh->kt = kt; sh->k = ks; }
+            }
+            double bm = 0.0, cm = 0.0;
+            for (int i = tid; i < m; i += NT) bm = fmax(bm, fabs(b[i]));
+            for (int j = tid; j < n; j += NT) cm = fmax(cm, fabs(c[j]));
+            __syncthreads();
+            const double bnorm = blk_max<NT>(bm, sh), cnorm = blk_max<NT>(cm, sh);
+            const int K = sh->k;
+            const double tol_p = a.tol_feas * (1.0 + bnorm);
+            const double tol_d = a.tol_opt * fmax(1.0, cnorm);
+            bool ok = sh->kt == K && sh->fail == 0;
+            double *M = nullptr;
+            if (ok) {
+                M = (mat_off + 8 * int64_t(K) * K <= a.lds_bytes)
+                        ? reinterpret_cast<double *>(smem + mat_off)
+                        : reinterpret_cast<double *>(a.scratch + int64_t(blockIdx.x) * a.slot_bytes);
+                // B_TS, row-major K x K, sign-normalised.
+                for (int e = tid; e < K * K; e += NT) {
+                    const int t = e / K, s2 = e - t * K;
+                    const int i = tlist[t];
+                    const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
+                    M[e] = sg * A[int64_t(i) * n + slist[s2]];
+                }
+                for (int t = tid; t < K; t += NT) {
+                    const int i = tlist[t];
+                    xs[t] = ((rowf[i] & kRowNeg) ? -1.0 : 1.0) * b[i];
+                    yt[t] = c[slist[t]];
+                    perm[t] = t;
+                }
+                double am = 0.0;
+                for (int e = tid; e < K * K; e += NT) am = fmax(am, fabs(M[e]));
+                __syncthreads();
+                const double amax = blk_max<NT>(am, sh);
+                // LU with partial pivoting (ties to the smaller row).
+                for (int p = 0; p < K; ++p) {
+                    double key = -1.0;
+                    int idx = kBig;
+                    for (int i = p + tid; i < K; i += NT) {
+                        const double v = fabs(M[i * K + p]);
+                        if (v > key || (v == key && i < idx)) { key = v; idx = i; }
+                    }
+                    blk_argmax<NT>(key, idx, sh);
+                    if (!(key > 1e-13 * fmax(1.0, amax))) { ok = false; break; }
+                    if (idx != p) {
+                        for (int j = tid; j < K; j += NT) {
+                            const double t0 = M[p * K + j];
+                            M[p * K + j] = M[idx * K + j];
+                            M[idx * K + j] = t0;
+                        }
+                        if (tid == 0) {
+                            const double t1 = xs[p]; xs[p] = xs[idx]; xs[idx] = t1;
+                            const int t2 = perm[p]; perm[p] = perm[idx]; perm[idx] = t2;
+                        }
+                    }
+                    __syncthreads();
+                    const double inv = 1.0 / M[p * K + p];
+                    for (int i = p + 1 + tid; i < K; i += NT) M[i * K + p] *= inv;
+                    __syncthreads();
+                    const int rem = K - p - 1;
+                    for (int e = tid; e < rem * rem; e += NT) {
+                        const int i = p + 1 + e / rem, j = p + 1 + e % rem;
+                        M[i * K + j] = fma(-M[i * K + p], M[p * K + j], M[i * K + j]);
+                    }
+                    __syncthreads();
+                }
+                if (!ok) cert |= LP_CERT_SINGULAR_BIT;
+            }
+            if (ok) {
+                // x_S: L z = P b_T (xs already permuted), U x = z.
+                for (int p = 0; p < K; ++p) {
+                    const double zp = xs[p];
+                    for (int i = p + 1 + tid; i < K; i += NT) xs[i] = fma(-M[i * K + p], zp, xs[i]);
+                    __syncthreads();
+                }
+                for (int p = K - 1; p >= 0; --p) {
+                    const double xp = xs[p] / M[p * K + p];
+                    __syncthreads();
+                    if (tid == 0) xs[p] = xp;
+                    for (int i = tid; i < p; i += NT) xs[i] = fma(-M[i * K + p], xp, xs[i]);
+                    __syncthreads();
+                }
+                // y_T: B^T y = c_S  ->  U^T w = c_S, L^T v = w, y = P^T v.
+                for (int p = 0; p < K; ++p) {
+                    const double wp = yt[p] / M[p * K + p];
+                    __syncthreads();
+                    if (tid == 0) yt[p] = wp;
+                    for (int j = p + 1 + tid; j < K; j += NT) yt[j] = fma(-M[p * K + j], wp, yt[j]);
+                    __syncthreads();
+                }
+                for (int p = K - 1; p >= 0; --p) {
+                    const double vp = yt[p];
+                    for (int j = tid; j < p; j += NT) yt[j] = fma(-M[p * K + j], vp, yt[j]);
+                    __syncthreads();
+                }
+                // Undo the row permutation: y for tight row tlist[perm[p]] is yt[p].
+                for (int p = tid; p < K; p += NT) wv[perm[p]] = yt[p];
+                __syncthreads();
+                for (int p = tid; p < K; p += NT) yt[p] = wv[p];
+                __syncthreads();
+
+                // Primal certificate.
+                bool pf = true;
+                for (int s2 = tid; s2 < K; s2 += NT) pf &= xs[s2] >= -tol_p;
+                for (int i = tid; i < m; i += NT) {
+                    const int f = rowf[i];
+                    if (f & kTight) continue;
+                    const double sg = (f & kRowNeg) ? -1.0 : 1.0;
+                    double ax = 0.0;
+                    for (int s2 = 0; s2 < K; ++s2) ax = fma(A[int64_t(i) * n + slist[s2]], xs[s2], ax);
+                    const double r = sg * (b[i] - ax);  // normalised slack b_i - a_i x
+                    const int sen = (f >> 1) & 3;
+                    if (f & kDeadRow) pf &= fabs(r) <= tol_p;
+                    else if (sen == kLE) pf &= r >= -tol_p;
+                    else if (sen == kGE) pf &= -r >= -tol_p;
+                }
+                if (!pf) sh->fail = 1;
+                __syncthreads();
+                const bool primal_ok = sh->fail == 0;
+                if (primal_ok) cert |= LP_CERT_PRIMAL_OK_BIT;
+                __syncthreads();
+
+                if (st0 == kOptimal && primal_ok) {
+                    // Dual certificate: reduced costs of every non-basic column.
+                    bool df = true;
+                    for (int j = tid; j < n; j += NT) {
+                        if (spos[j] >= 0) continue;
+                        double ya = 0.0;
+                        for (int t = 0; t < K; ++t) {
+                            const int i = tlist[t];
+                            const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
+                            ya = fma(yt[t], sg * A[int64_t(i) * n + j], ya);
+                        }
+                        df &= c[j] - ya <= tol_d;
+                    }
+                    for (int t = tid; t < K; t += NT) {
+                        const int sen = (rowf[tlist[t]] >> 1) & 3;
+                        if (sen == kLE) df &= -yt[t] <= tol_d;
+                        else if (sen == kGE) df &= yt[t] <= tol_d;
+                    }
+                    if (!df) sh->fail = 2;
+                    __syncthreads();
+                    if (sh->fail == 0) cert |= LP_CERT_DUAL_OK_BIT;
+                } else if (st0 == kUnbounded && primal_ok) {
+                    // Ray of the entering variable q.
+                    const int q = a.enter[k];
+                    bool rf = q >= 0 && q < n + m && !(q < n && spos[q] >= 0);
+                    int tr = -1;
+                    double sq = 0.0;
+                    if (rf && q >= n) {
+                        tr = tpos[q - n];
+                        const int sen = (rowf[q - n] >> 1) & 3;
+                        rf = tr >= 0 && sen != kEQ;
+                        sq = (sen == kLE) ? 1.0 : -1.0;
+                    }
+                    if (rf) {
+                        // wv = B^-1 a_q restricted to T (then d_S = -wv).
+                        for (int t = tid; t < K; t += NT) {
+                            const int i = tlist[t];
+                            const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
+                            yt[t] = (q < n) ? sg * A[int64_t(i) * n + q] : (t == tr ? sq : 0.0);
+                        }
+                        __syncthreads();
+                        if (tid == 0)
+                            for (int p = 0; p < K; ++p) {  // apply the row permutation
+                                wv[p] = yt[perm[p]];
+                            }
+                        __syncthreads();
+                        for (int p = 0; p < K; ++p) {
+                            const double zp = wv[p];
+                            for (int i = p + 1 + tid; i < K; i += NT) wv[i] = fma(-M[i * K + p], zp, wv[i]);
+                            __syncthreads();
+                        }
+                        for (int p = K - 1; p >= 0; --p) {
+                            const double xp = wv[p] / M[p * K + p];
+                            __syncthreads();
+                            if (tid == 0) wv[p] = xp;
+                            for (int i = tid; i < p; i += NT) wv[i] = fma(-M[i * K + p], xp, wv[i]);
+                            __syncthreads();
+                        }
+                        const double tol_r = a.tol_feas;
+                        bool ok2 = true;
+                        double gain = 0.0;
+                        for (int s2 = tid; s2 < K; s2 += NT) {
+                            ok2 &= -wv[s2] >= -tol_r;
+                            gain = fma(c[slist[s2]], -wv[s2], gain);
+                        }
+                        for (int i = tid; i < m; i += NT) {
+                            const int f = rowf[i];
+                            if (f & kTight) continue;
+                            const double sg = (f & kRowNeg) ? -1.0 : 1.0;
+                            double ad = (q < n) ? A[int64_t(i) * n + q] : 0.0;
+                            for (int s2 = 0; s2 < K; ++s2) ad = fma(A[int64_t(i) * n + slist[s2]], -wv[s2], ad);
+                            const double dr = -sg * ad;  // change of the normalised slack
+                            const int sen = (f >> 1) & 3;
+                            if (f & kDeadRow) ok2 &= fabs(dr) <= tol_r;
+                            else if (sen == kLE) ok2 &= dr >= -tol_r;
+                            else if (sen == kGE) ok2 &= -dr >= -tol_r;
+                        }
+                        if (!ok2) sh->fail = 3;
+                        double g = gain;
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off);
+                        if constexpr (NT > 64) {
+                            if (lane == 0) sh->rd[wave] = g;
+                            __syncthreads();
+                            g = 0.0;
+                            for (int qq = 0; qq < NT / 64; ++qq) g += sh->rd[qq];
+                        }
+                        __syncthreads();
+                        const double cq = (q < n) ? c[q] : 0.0;
+                        if (sh->fail == 0 && cq + g > tol_d) cert |= LP_CERT_RAY_OK_BIT;
+                        __syncthreads();
+                    }
+                }
+            }
+            const bool passed = (st0 == kOptimal) ? (cert & LP_CERT_DUAL_OK_BIT) && (cert & LP_CERT_PRIMAL_OK_BIT)
+                                                  : (cert & LP_CERT_RAY_OK_BIT) != 0;
+            fallback = !passed;
+            if (passed && st0 == kOptimal) {
+                // FP64 x and objective (fixed summation order by wavefront 0).
+                for (int j = tid; j < n; j += NT) x[j] = (spos[j] >= 0) ? xs[spos[j]] : 0.0;
+                if (wave == 0) {
+                    double z = 0.0;
+                    for (int j = lane; j < n; j += 64) z = fma(c[j], (spos[j] >= 0) ? xs[spos[j]] : 0.0, z);
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off);
+                    if (lane == 0) a.obj[k] = z;
+                }
+            } else if (passed) {
+                for (int j = tid; j < n; j += NT) x[j] = __builtin_nan("");
+                if (tid == 0) a.obj[k] = __builtin_inf();
+            }
+        }
+        if (tid == 0) {
+            if (a.stats) a.stats[8 * k + 5] = cert;
+            if (fallback) {
+                const int slot = atomicAdd(a.fb_count, 1);
+                a.fb_ids[slot] = int32_t(k);
+            }
+        }
+        __syncthreads();
+        item = sh->next;
+        __syncthreads();
+    }
+    if (tid == 0) finish_launch(a.queue, a.done, nullptr);
+}
+
+template <int NT>
+hipError_t launch_t(const CertArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((certify_kernel<NT>), dim3(grid), dim3(NT), a.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+template <int NT>
+int occ_t(int lds)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)certify_kernel<NT>, NT, lds) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+}  // namespace
+
+int64_t certify_lds_bytes(int m, int n, bool with_matrix)
+{
+    const int kmax = m < n ? m : n;
+    int64_t v = align16(sizeof(CertCtrl<256>)) + align16(4 * int64_t(3 * m + 3 * n)) +
+                align16(8 * 3 * int64_t(kmax) + 4 * int64_t(kmax));
+    if (with_matrix) v += 8 * int64_t(kmax) * kmax;
+    return v;
+}
+
+hipError_t launch_certify(int nt, const CertArgs &a, int grid, hipStream_t s)
+{
+    return nt == 64 ? launch_t<64>(a, grid, s) : launch_t<256>(a, grid, s);
+}
+
+int certify_blocks_per_cu(int nt, int lds) { return nt == 64 ? occ_t<64>(lds) : occ_t<256>(lds); }
+
+hipError_t certify_configure(int max_lds)
+{
+    const void *fns[] = {(const void *)certify_kernel<64>, (const void *)certify_kernel<256>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace lpb

@@ -11,6 +11,9 @@ constexpr int kOptimal = 0, kInfeasible = 1, kUnbounded = 2, kIterLimit = 3, kNu
               kInvalid = 5;
 constexpr int kBig = 0x7fffffff;
 constexpr int kRowNeg = 1, kRowDead = 8, kRowPad = 16;
+// Certificate outcome bits (stats[5]); the values of LP_CERT_* in lpbatch.h.
+constexpr int LP_CERT_PRIMAL_OK_BIT = 1, LP_CERT_DUAL_OK_BIT = 2, LP_CERT_RAY_OK_BIT = 4,
+              LP_CERT_SINGULAR_BIT = 8;
 
 template <typename T> __device__ __forceinline__ T t_inf();
 template <> __device__ __forceinline__ float t_inf<float>() { return __builtin_inff(); }
@@ -151,6 +154,20 @@ __device__ __forceinline__ T wave_max_f(T v)
     v = fmax(a, b);
     swap32_f(v, a, b);
     return fmax(a, b);
+}
+
+// Called once per workgroup (one thread) when it leaves its work loop: the
+// last workgroup to finish returns the launch's counters to 0 for the next
+// launch on the stream.  Every queue atomic of a workgroup has returned
+// before it gets here (its result decides the loop exit).
+__device__ __forceinline__ void finish_launch(int32_t *queue, int32_t *done, int32_t *extra)
+{
+    const int fin = atomicAdd(done, 1);
+    if (fin == int(gridDim.x) - 1) {
+        atomicExch(queue, 0);
+        atomicExch(done, 0);
+        if (extra) atomicExch(extra, 0);
+    }
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane)

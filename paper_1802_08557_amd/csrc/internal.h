@@ -20,7 +20,8 @@ struct SolveParams {
 struct SolveArgs {
     int64_t num;              // work items in this launch (upper bound if num_dev is set)
     const int32_t *ids;       // work item -> LP index; null: identity
-    const int32_t *num_dev;   // optional device-side item count (<= num)
+    const int32_t *num_dev;   // optional device-side count: items = id_base + *num_dev
+    int32_t id_base;
     const double *A, *b, *c;  // batch data, layout of include/lpbatch.h
     const int8_t *sense;
     int32_t um, un;           // > 0: every LP is um x un (offsets computed, m/n/offsets unused)
@@ -33,13 +34,45 @@ struct SolveArgs {
     int32_t *enter_out;       // optional [num_lps]: entering Bland index at UNBOUNDED
     char *scratch;            // HBM tableau slots, one per workgroup of the launch
     int64_t slot_bytes;
-    int32_t *queue;           // work counter, zeroed before the launch
-    int32_t *defer_ids;       // wavefront kernel: LPs it could not take are appended here
-    int32_t *defer_count;     //   (the workgroup kernel then drains them)
+    int32_t *queue;           // work counter (0 at launch)
+    int32_t *done;            // finished workgroups (0 at launch); the last one to finish
+                              // resets queue, done and reset_extra to 0 for the next launch
+    int32_t *reset_extra;     // optional
+    int32_t *defer_ids;       // wavefront kernel: LPs it could not take are appended here,
+    int32_t *defer_count;     //   from defer_ids[defer_base] on (the workgroup kernel
+    int32_t defer_base;       //   then drains them)
     int32_t lds_bytes;        // dynamic LDS of each workgroup
     int32_t force_hbm;        // 1: never keep the tableau in LDS
+    int32_t refine_stats;     // 1: a re-solve -- pivots go to stats[4], stats[3] = 1
     SolveParams prm;
 };
+
+// One launch of the FP64 certificate kernel (certify_kernels.hip).
+struct CertArgs {
+    int64_t num;
+    const double *A, *b, *c;
+    const int8_t *sense;
+    int32_t um, un;
+    const int32_t *m, *n;
+    const int64_t *aoff, *roff, *coff;
+    int32_t *status;
+    double *x, *obj;
+    int32_t *stats;
+    const int32_t *basis;     // final basis of the single-precision solve
+    const int32_t *enter;     // entering variable at UNBOUNDED
+    int32_t *fb_ids;          // LPs to re-solve in FP64 are appended here
+    int32_t *fb_count;
+    char *scratch;            // LU matrices too large for LDS, one slot per workgroup
+    int64_t slot_bytes;
+    int32_t *queue, *done;
+    int32_t lds_bytes;
+    double tol_feas, tol_opt; // certificate tolerances (relative, as in SolveParams)
+};
+
+hipError_t launch_certify(int nt, const CertArgs &a, int grid, hipStream_t s);
+int certify_blocks_per_cu(int nt, int lds_bytes);
+int64_t certify_lds_bytes(int m, int n, bool with_matrix);
+hipError_t certify_configure(int max_lds);
 
 // Bland index convention shared by every kernel: structural j -> j, the
 // slack/surplus of row i -> n + i, the artificial of row i -> n + m + i.

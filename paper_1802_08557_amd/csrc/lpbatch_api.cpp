@@ -77,6 +77,7 @@ struct KernelTime {
 
 struct lp_ctx {
     int device = 0;
+    bool counters_dirty = false;  // a failed call may have left work counters non-zero
     int num_cu = 0;
     int max_lds = 0;
     DevBuf scratch, meta, counters;
@@ -147,6 +148,117 @@ lpb::SolveParams fill_params(const lp_options &o, bool fp32)
     return p;
 }
 
+// A validated batch as the planner sees it.
+struct Plan {
+    int64_t num;
+    bool uniform;
+    int32_t m0, n0, m_max, n_max;
+    bool fp32;
+    int64_t ts;
+};
+
+// Counters of one solve pass (wavefront kernel + workgroup kernel).
+struct PassCounters {
+    int32_t *wq, *wd;  // wavefront queue / finished
+    int32_t *bq, *bd;  // workgroup queue / finished
+    int32_t *defer;    // LPs deferred by the wavefront kernel
+};
+
+bool wave_fit(const lp_ctx *ctx, int64_t mk, int64_t nk, bool fp32)
+{
+    const int64_t ts = fp32 ? 4 : 8;
+    return nk <= 63 && mk <= 128 &&
+           lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, fp32) + mk * lpb::tableau_ld(int(nk) + 1) * ts <=
+               ctx->max_lds;
+}
+
+// Queues one solve pass.  The LPs are either the n_wave + n_block LPs given by
+// host-built id lists already on the device (wave_ids, and block ids at the
+// front of defer_ids), or -- when list_count is set -- the device list
+// list_ids[0 .. *list_count), all offered to the wavefront kernel first.
+int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &opts, PassCounters pc,
+               const int32_t *wave_ids, int64_t n_wave, int wm_max, int wn_max, int64_t n_block,
+               int32_t *defer_ids, const int32_t *list_ids, const int32_t *list_count,
+               hipStream_t stream, bool timing, const char *wname, const char *bname)
+{
+    const bool fp32 = P.fp32;
+    const int64_t ts = P.ts;
+    if (n_wave > 0) {
+        const int rb = wm_max > 64 ? 2 : 1;
+        lpb::SolveArgs w = a;
+        w.num = list_count ? P.num : n_wave;
+        w.ids = list_count ? list_ids : wave_ids;
+        w.num_dev = list_count;
+        w.id_base = 0;
+        w.queue = pc.wq;
+        w.done = pc.wd;
+        w.reset_extra = const_cast<int32_t *>(list_count);  // nothing reads it after this launch
+        w.defer_ids = defer_ids;
+        w.defer_count = pc.defer;
+        w.defer_base = int32_t(n_block);
+        const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) + int64_t(wm_max) * lpb::tableau_ld(wn_max + 1) * ts;
+        w.lds_bytes = int32_t(lds);
+        const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
+        if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
+        const int64_t grid = std::min<int64_t>(w.num, int64_t(per_cu) * ctx->num_cu);
+        Timer t(ctx, timing, stream, wname);
+        HIP_TRY(lpb::launch_simplex_wave(fp32, rb, w, int(grid), stream));
+        t.done();
+    }
+    // Workgroup kernel: the LPs given to it plus the ones the wavefront deferred.
+    const int ncol_worst = P.n_max + P.m_max;
+    lpb::LdsLayout L = lpb::lds_layout(P.m_max, ncol_worst, ts, lpb::simplex_ctrl_bytes(fp32));
+    // Tableau budget for the common case of no surplus columns (every row <= after
+    // normalisation); LPs with more columns than budgeted move to HBM by themselves.
+    const int64_t tab_common = int64_t(P.m_max + 1) * lpb::tableau_ld(P.n_max + 1) * ts;
+    const int64_t tab_worst = int64_t(P.m_max + 1) * lpb::tableau_ld(ncol_worst + 1) * ts;
+    const int64_t cells = int64_t(P.m_max + 1) * (P.n_max + 1);
+    int nt = opts.block_threads;
+    if (!nt) nt = cells <= 64 * 64 ? 64 : (cells <= 256 * 256 ? 256 : 512);
+    int64_t lds = L.tab;
+    const bool want_lds = opts.placement != LP_PLACE_HBM && L.tab + tab_common <= ctx->max_lds;
+    if (want_lds) lds = L.tab + tab_common;
+    if (lds > ctx->max_lds)
+        return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index "
+                    "arrays (device limit %d)", P.m_max, ncol_worst, (long long)lds, ctx->max_lds);
+    a.lds_bytes = int32_t(lds);
+    a.force_hbm = opts.placement == LP_PLACE_HBM;
+    const int per_cu = lpb::simplex_blocks_per_cu(fp32, nt, int(lds));
+    if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for %d threads, %lld B LDS", nt, (long long)lds);
+    // When the wavefront kernel was offered every LP, this launch only drains
+    // the few it deferred: one workgroup per CU is plenty and keeps its end cheap.
+    const int64_t slots = n_wave > 0 && n_block == 0 ? ctx->num_cu : int64_t(per_cu) * ctx->num_cu;
+    const int64_t grid = std::min<int64_t>(P.num, slots);
+    const bool need_hbm = !want_lds || tab_worst > tab_common;
+    if (need_hbm) {
+        a.slot_bytes = lpb::align16(tab_worst);
+        int rc = ctx->scratch.ensure(size_t(a.slot_bytes) * size_t(grid));
+        if (rc != LP_OK) return rc;
+        a.scratch = static_cast<char *>(ctx->scratch.p);
+    }
+    a.queue = pc.bq;
+    a.done = pc.bd;
+    a.num = P.num;
+    if (n_wave > 0) {
+        a.ids = defer_ids;
+        a.id_base = int32_t(n_block);
+        a.num_dev = pc.defer;
+        a.reset_extra = pc.defer;
+    } else if (list_count) {
+        a.ids = list_ids;
+        a.id_base = 0;
+        a.num_dev = list_count;
+        a.reset_extra = const_cast<int32_t *>(list_count);
+    } else {
+        a.ids = n_block < P.num ? defer_ids : nullptr;
+        a.num = n_block;
+    }
+    Timer t(ctx, timing, stream, bname);
+    HIP_TRY(lpb::launch_simplex(fp32, nt, a, int(grid), stream));
+    t.done();
+    return LP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -179,11 +291,15 @@ int lp_ctx_create(lp_ctx **out, int device)
         return fail(LP_ERR_HIP, "lp_ctx_create: device attribute query failed");
     }
     if (lpb::simplex_configure(ctx->max_lds) != hipSuccess ||
-        lpb::simplex_wave_configure(ctx->max_lds) != hipSuccess) {
+        lpb::simplex_wave_configure(ctx->max_lds) != hipSuccess ||
+        lpb::certify_configure(ctx->max_lds) != hipSuccess) {
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: could not configure kernel LDS limits");
     }
     int rc = ctx->counters.ensure(4096);
+    if (rc == LP_OK && (lpb::launch_zero_i32(static_cast<int32_t *>(ctx->counters.p), 1024, nullptr) != hipSuccess ||
+                        hipStreamSynchronize(nullptr) != hipSuccess))
+        rc = fail(LP_ERR_HIP, "lp_ctx_create: could not clear the work counters");
     if (rc != LP_OK) {
         delete ctx;
         return rc;
@@ -225,50 +341,45 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         return fail(LP_ERR_ARG, "a batch pointer is NULL");
     if (num_lps > INT32_MAX) return fail(LP_ERR_ARG, "num_lps exceeds 2^31-1");
 
-    // Shapes (host arrays), offsets and the uniform-shape shortcut.
-    int32_t m0 = m[0], n0 = n[0], m_max = 0, n_max = 0;
-    bool uniform = true;
-    int64_t sa = 0, sr = 0, sc = 0;
+    // Shapes (host arrays) and the uniform-shape shortcut.
+    Plan P;
+    P.num = num_lps;
+    P.m0 = m[0]; P.n0 = n[0]; P.m_max = 0; P.n_max = 0;
+    P.uniform = true;
+    int64_t sa = 0;
     for (int64_t k = 0; k < num_lps; ++k) {
         const int32_t mk = m[k], nk = n[k];
         if (mk < 1 || nk < 1)
             return fail(LP_ERR_ARG, "LP %lld has m=%d n=%d (both must be >= 1)", (long long)k, mk, nk);
         if (mk > 1000000 || nk > 1000000)
             return fail(LP_ERR_ARG, "LP %lld is too large (m=%d n=%d)", (long long)k, mk, nk);
-        uniform = uniform && mk == m0 && nk == n0;
-        m_max = std::max(m_max, mk);
-        n_max = std::max(n_max, nk);
+        P.uniform = P.uniform && mk == P.m0 && nk == P.n0;
+        P.m_max = std::max(P.m_max, mk);
+        P.n_max = std::max(P.n_max, nk);
         sa += int64_t(mk) * nk;
-        sr += mk;
-        sc += nk;
-        if (sa < 0 || sa > (int64_t(1) << 60)) return fail(LP_ERR_ARG, "batch size overflows");
+        if (sa > (int64_t(1) << 60)) return fail(LP_ERR_ARG, "batch size overflows");
     }
-    const bool fp32 = opts.precision == LP_PREC_FP32_CERT64;
-    if (fp32) return fail(LP_ERR_ARG, "LP_PREC_FP32_CERT64 is not available in this build");
+    P.fp32 = opts.precision == LP_PREC_FP32_CERT64;
+    P.ts = P.fp32 ? 4 : 8;
     hipStream_t stream = reinterpret_cast<hipStream_t>(opts.stream);
     DeviceGuard g(ctx->device);
-    const int64_t ts = fp32 ? 4 : 8;
 
     // Kernel choice per LP: one wavefront for LPs of at most 63 columns and 128
     // rows whose tableau fits LDS, a workgroup otherwise (or when the caller
     // fixes the workgroup size or asks for HBM placement).
     const bool auto_kernel = opts.block_threads == 0 && opts.placement != LP_PLACE_HBM;
-    auto wave_fit = [&](int64_t mk, int64_t nk) {
-        return nk <= 63 && mk <= 128 &&
-               lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, fp32) + mk * lpb::tableau_ld(int(nk) + 1) * ts <=
-                   ctx->max_lds;
-    };
     std::vector<int32_t> wave_ids, block_ids;
-    int64_t n_wave = 0;
+    int64_t n_wave = 0, rows = 0;
     int wm_max = 0, wn_max = 0;
     for (int64_t k = 0; k < num_lps; ++k) {
-        const bool w = auto_kernel && wave_fit(m[k], n[k]);
+        const bool w = auto_kernel && wave_fit(ctx, m[k], n[k], P.fp32);
         if (w) {
             ++n_wave;
             wm_max = std::max(wm_max, m[k]);
             wn_max = std::max(wn_max, n[k]);
         }
-        if (!uniform) (w ? wave_ids : block_ids).push_back(int32_t(k));
+        rows += m[k];
+        if (!P.uniform) (w ? wave_ids : block_ids).push_back(int32_t(k));
     }
     const int64_t n_block = num_lps - n_wave;
 
@@ -277,24 +388,31 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     a.A = A; a.b = b; a.c = c; a.sense = sense;
     a.status = status; a.x = x; a.obj = obj;
     a.stats = opts.stats;
-    a.prm = fill_params(opts, fp32);
+    a.prm = fill_params(opts, P.fp32);
 
-    // Device metadata: [m][n][aoff][roff][coff] (non-uniform only), then the
-    // wavefront id list and the deferred/workgroup id list (capacity num_lps).
-    const size_t sz_shape = uniform ? 0 : size_t(num_lps) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
+    // Device metadata: [m][n][aoff][roff][coff] (non-uniform only); id lists
+    // (capacity num_lps each): wavefront ids, deferred/workgroup ids, fallback
+    // ids, deferred ids of the fallback pass; FP32 final bases [rows] and
+    // entering variables [num_lps].
+    const size_t sz_shape = P.uniform ? 0 : size_t(num_lps) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
     const size_t sz_ids = size_t(num_lps) * sizeof(int32_t);
+    const size_t sz_fp32 = P.fp32 ? lpb::align16(size_t(rows) * 4) + lpb::align16(sz_ids) : 0;
     {
-        int rc = ctx->meta.ensure(sz_shape + 2 * sz_ids);
+        int rc = ctx->meta.ensure(sz_shape + 4 * lpb::align16(sz_ids) + sz_fp32);
         if (rc != LP_OK) return rc;
     }
     char *meta = static_cast<char *>(ctx->meta.p);
     int32_t *d_wave_ids = reinterpret_cast<int32_t *>(meta + sz_shape);
-    int32_t *d_defer_ids = d_wave_ids + num_lps;
-    if (uniform) {
-        a.um = m0;
-        a.un = n0;
+    int32_t *d_defer_ids = reinterpret_cast<int32_t *>(meta + sz_shape + lpb::align16(sz_ids));
+    int32_t *d_fb_ids = reinterpret_cast<int32_t *>(meta + sz_shape + 2 * lpb::align16(sz_ids));
+    int32_t *d_fb_defer = reinterpret_cast<int32_t *>(meta + sz_shape + 3 * lpb::align16(sz_ids));
+    int32_t *d_basis = reinterpret_cast<int32_t *>(meta + sz_shape + 4 * lpb::align16(sz_ids));
+    int32_t *d_enter = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(d_basis) + lpb::align16(size_t(rows) * 4));
+    if (P.uniform) {
+        a.um = P.m0;
+        a.un = P.n0;
     } else {
-        std::vector<char> host(sz_shape + sz_ids + size_t(n_block) * sizeof(int32_t));
+        std::vector<char> host(sz_shape + lpb::align16(sz_ids) + size_t(n_block) * sizeof(int32_t));
         int32_t *hm = reinterpret_cast<int32_t *>(host.data());
         int32_t *hn = hm + num_lps;
         int64_t *ha = reinterpret_cast<int64_t *>(hn + num_lps);
@@ -307,7 +425,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         }
         int32_t *hw = reinterpret_cast<int32_t *>(host.data() + sz_shape);
         std::copy(wave_ids.begin(), wave_ids.end(), hw);
-        int32_t *hb = hw + num_lps;
+        int32_t *hb = reinterpret_cast<int32_t *>(host.data() + sz_shape + lpb::align16(sz_ids));
         std::copy(block_ids.begin(), block_ids.end(), hb);
         HIP_TRY(hipMemcpyAsync(meta, host.data(), host.size(), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));  // the host staging buffer goes away
@@ -317,73 +435,87 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         a.roff = a.aoff + num_lps;
         a.coff = a.roff + num_lps;
     }
-    int32_t *cnt = static_cast<int32_t *>(ctx->counters.p);  // [0] wave queue, [1] block queue, [2] deferred
+    // Work counters, each returned to 0 by the last workgroup of its launch.
+    int32_t *cnt = static_cast<int32_t *>(ctx->counters.p);
+    PassCounters main_pc{cnt + 0, cnt + 1, cnt + 2, cnt + 3, cnt + 4};
+    PassCounters fb_pc{cnt + 16, cnt + 17, cnt + 18, cnt + 19, cnt + 20};
+    int32_t *cert_q = cnt + 8, *cert_d = cnt + 9, *fb_count = cnt + 10;
     const bool timing = (opts.flags & LP_FLAG_TIME_KERNELS) != 0;
-
-    if (n_wave > 0) {
-        const int rb = wm_max > 64 ? 2 : 1;
-        lpb::SolveArgs w = a;
-        w.num = n_wave;
-        w.ids = uniform ? nullptr : d_wave_ids;
-        w.queue = cnt;
-        w.defer_ids = d_defer_ids;
-        w.defer_count = cnt + 2;
-        const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) +
-                            int64_t(wm_max) * lpb::tableau_ld(wn_max + 1) * ts;
-        w.lds_bytes = int32_t(lds);
-        const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
-        if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
-        const int64_t grid = std::min<int64_t>(n_wave, int64_t(per_cu) * ctx->num_cu);
-        HIP_TRY(lpb::launch_zero_i32(cnt, 1, stream));
-        HIP_TRY(lpb::launch_set_i32(cnt + 2, int32_t(n_block), stream));
-        Timer t(ctx, timing, stream, fp32 ? "simplex_wave_fp32" : "simplex_wave_fp64");
-        HIP_TRY(lpb::launch_simplex_wave(fp32, rb, w, int(grid), stream));
-        t.done();
+    if (ctx->counters_dirty) {
+        HIP_TRY(lpb::launch_zero_i32(cnt, 1024, stream));
+        ctx->counters_dirty = false;
     }
+    ctx->counters_dirty = true;  // until every launch below has been queued
 
-    // Workgroup kernel: every LP not given to a wavefront, plus the deferred ones.
-    const int ncol_worst = n_max + m_max;
-    lpb::LdsLayout L = lpb::lds_layout(m_max, ncol_worst, ts, lpb::simplex_ctrl_bytes(fp32));
-    // Tableau budget for the common case of no surplus columns (every row <= after
-    // normalisation); LPs with more columns than budgeted move to HBM by themselves.
-    const int64_t tab_common = int64_t(m_max + 1) * lpb::tableau_ld(n_max + 1) * ts;
-    const int64_t tab_worst = int64_t(m_max + 1) * lpb::tableau_ld(ncol_worst + 1) * ts;
-    const int64_t cells = int64_t(m_max + 1) * (n_max + 1);
-    int nt = opts.block_threads;
-    if (!nt) nt = cells <= 64 * 64 ? 64 : (cells <= 256 * 256 ? 256 : 512);
-    int64_t lds = L.tab;
-    const bool want_lds = opts.placement != LP_PLACE_HBM && L.tab + tab_common <= ctx->max_lds;
-    if (want_lds) lds = L.tab + tab_common;
-    if (lds > ctx->max_lds)
-        return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index "
-                    "arrays (device limit %d)", m_max, ncol_worst, (long long)lds, ctx->max_lds);
-    a.lds_bytes = int32_t(lds);
-    a.force_hbm = opts.placement == LP_PLACE_HBM;
-    const int per_cu = lpb::simplex_blocks_per_cu(fp32, nt, int(lds));
-    if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for %d threads, %lld B LDS", nt, (long long)lds);
-    const int64_t grid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
-    const bool need_hbm = !want_lds || tab_worst > tab_common;
-    if (need_hbm) {
-        a.slot_bytes = lpb::align16(tab_worst);
-        int rc = ctx->scratch.ensure(size_t(a.slot_bytes) * size_t(grid));
+    if (P.fp32) {
+        a.basis_out = d_basis;
+        a.enter_out = d_enter;
+    }
+    int rc = queue_pass(ctx, P, a, opts, main_pc, P.uniform ? nullptr : d_wave_ids, n_wave, wm_max, wn_max,
+                        n_block, d_defer_ids,
+                        nullptr, nullptr, stream, timing, P.fp32 ? "simplex_wave_fp32" : "simplex_wave_fp64",
+                        P.fp32 ? "simplex_block_fp32" : "simplex_block_fp64");
+    if (rc != LP_OK) return rc;
+
+    if (P.fp32) {
+        // FP64 certificate of every final basis, then an FP64 re-solve of the rest.
+        lpb::CertArgs ca;
+        std::memset(&ca, 0, sizeof ca);
+        ca.num = num_lps;
+        ca.A = A; ca.b = b; ca.c = c; ca.sense = sense;
+        ca.um = a.um; ca.un = a.un; ca.m = a.m; ca.n = a.n;
+        ca.aoff = a.aoff; ca.roff = a.roff; ca.coff = a.coff;
+        ca.status = status; ca.x = x; ca.obj = obj; ca.stats = opts.stats;
+        ca.basis = d_basis; ca.enter = d_enter;
+        ca.fb_ids = d_fb_ids; ca.fb_count = fb_count;
+        ca.queue = cert_q; ca.done = cert_d;
+        const lpb::SolveParams p64 = fill_params(opts, false);
+        ca.tol_feas = p64.tol_feas;
+        ca.tol_opt = p64.tol_opt;
+        const int kmax = std::min(P.m_max, P.n_max);
+        const int cnt_nt = kmax <= 32 ? 64 : 256;
+        int64_t clds = lpb::certify_lds_bytes(P.m_max, P.n_max, true);
+        if (clds > std::min<int64_t>(ctx->max_lds, 64 * 1024)) clds = lpb::certify_lds_bytes(P.m_max, P.n_max, false);
+        if (clds > ctx->max_lds) return fail(LP_ERR_ARG, "LP too large for the certificate kernel");
+        ca.lds_bytes = int32_t(clds);
+        const int per_cu = lpb::certify_blocks_per_cu(cnt_nt, int(clds));
+        if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
+        const int64_t cgrid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
+        ca.slot_bytes = lpb::align16(8 * int64_t(kmax) * kmax);
+        {
+            // The LU slots share the tableau scratch (the FP32 pass has finished with it
+            // by the time the certificate kernel runs on the same stream).
+            int rc2 = ctx->scratch.ensure(std::max<size_t>(ctx->scratch.bytes, size_t(ca.slot_bytes) * size_t(cgrid)));
+            if (rc2 != LP_OK) return rc2;
+            ca.scratch = static_cast<char *>(ctx->scratch.p);
+        }
+        {
+            Timer t(ctx, timing, stream, "certify_fp64");
+            HIP_TRY(lpb::launch_certify(cnt_nt, ca, int(cgrid), stream));
+            t.done();
+        }
+        Plan P64 = P;
+        P64.fp32 = false;
+        P64.ts = 8;
+        lpb::SolveArgs a64 = a;
+        a64.prm = fill_params(opts, false);
+        a64.basis_out = nullptr;
+        a64.enter_out = nullptr;
+        a64.refine_stats = 1;
+        int64_t n_wave64 = 0;
+        int wm64 = 0, wn64 = 0;
+        for (int64_t k = 0; k < num_lps && auto_kernel; ++k)
+            if (wave_fit(ctx, m[k], n[k], false)) {
+                ++n_wave64;
+                wm64 = std::max(wm64, m[k]);
+                wn64 = std::max(wn64, n[k]);
+            }
+        rc = queue_pass(ctx, P64, a64, opts, fb_pc, nullptr, n_wave64 > 0 ? 1 : 0, wm64, wn64, 0, d_fb_defer,
+                        d_fb_ids, fb_count, stream, timing, "simplex_wave_fp64_resolve",
+                        "simplex_block_fp64_resolve");
         if (rc != LP_OK) return rc;
-        a.scratch = static_cast<char *>(ctx->scratch.p);
     }
-    a.queue = cnt + 1;
-    if (n_wave > 0) {
-        a.num = num_lps;  // upper bound; the deferred count is read on the device
-        a.ids = d_defer_ids;
-        a.num_dev = cnt + 2;
-    } else {
-        a.num = num_lps;
-        a.ids = nullptr;
-    }
-    HIP_TRY(lpb::launch_zero_i32(cnt + 1, 1, stream));
-    {
-        Timer t(ctx, timing, stream, fp32 ? "simplex_block_fp32" : "simplex_block_fp64");
-        HIP_TRY(lpb::launch_simplex(fp32, nt, a, int(grid), stream));
-        t.done();
-    }
+    ctx->counters_dirty = false;
     if (opts.flags & LP_FLAG_SYNC) HIP_TRY(hipStreamSynchronize(stream));
     return LP_OK;
 }

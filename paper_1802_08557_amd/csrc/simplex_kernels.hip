@@ -35,6 +35,7 @@
 // Phase II prices c out over the basis and continues.
 #include <math.h>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace lpb {
@@ -45,10 +46,6 @@ constexpr int ST_OPTIMAL = 0, ST_INFEASIBLE = 1, ST_UNBOUNDED = 2, ST_ITER = 3,
               ST_NUMERICAL = 4, ST_INVALID = 5;
 constexpr int BIG = 0x7fffffff;
 constexpr int ROW_NEG = 1, ROW_DEAD = 8;
-
-template <typename T> __device__ __forceinline__ T t_inf();
-template <> __device__ __forceinline__ float t_inf<float>() { return __builtin_inff(); }
-template <> __device__ __forceinline__ double t_inf<double>() { return __builtin_inf(); }
 
 template <typename T>
 struct Ctrl {
@@ -65,20 +62,6 @@ struct Ctrl {
 __device__ __forceinline__ int row_sense(int f) { return (f >> 1) & 3; }
 
 // ---- reductions ------------------------------------------------------------
-
-// Lexicographic argmin over the wavefront of (k1, k2), carrying a position.
-// Keys are unique or all-invalid, so every lane ends with the same winner.
-template <typename T>
-__device__ __forceinline__ void wave_argmin(T &k1, int &k2, int &p)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        T o1 = __shfl_xor(k1, off);
-        int o2 = __shfl_xor(k2, off);
-        int op = __shfl_xor(p, off);
-        if (o1 < k1 || (o1 == k1 && o2 < k2)) { k1 = o1; k2 = o2; p = op; }
-    }
-}
 
 template <typename T, int NT>
 __device__ __forceinline__ void block_argmin(T &k1, int &k2, int &p, Ctrl<T> *sh)
@@ -376,12 +359,17 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
             if (a.enter_out) a.enter_out[P.k] = (status == ST_UNBOUNDED) ? enter : -1;
             if (a.stats) {
                 int32_t *st = a.stats + 8 * P.k;
-                st[0] = P.it1;
-                st[1] = P.iters - P.it1;
-                st[2] = P.degp;
-                st[3] = 0;
-                st[4] = 0;
-                st[5] = 0;
+                if (a.refine_stats) {
+                    st[3] = 1;
+                    st[4] = P.iters;
+                } else {
+                    st[0] = P.it1;
+                    st[1] = P.iters - P.it1;
+                    st[2] = P.degp;
+                    st[3] = 0;
+                    st[4] = 0;
+                    st[5] = 0;
+                }
                 st[6] = placement;
                 st[7] = nbs;
             }
@@ -399,7 +387,7 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     Ctrl<T> *sh = reinterpret_cast<Ctrl<T> *>(smem);
-    const int64_t total = a.num_dev ? int64_t(*a.num_dev) : a.num;
+    const int64_t total = a.num_dev ? int64_t(a.id_base) + *a.num_dev : a.num;
     int64_t item = blockIdx.x;
     while (item < total) {
         if (tid == 0) sh->next = gridDim.x + atomicAdd(a.queue, 1);
@@ -479,6 +467,7 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         item = sh->next;
         __syncthreads();
     }
+    if (tid == 0) finish_launch(a.queue, a.done, a.reset_extra);
 }
 
 __global__ void zero_i32_kernel(int32_t *p, int count)

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
     T *xv = reinterpret_cast<T *>(smem + align16(4 * 64 * RB));
     double *cl = reinterpret_cast<double *>(smem + align16(4 * 64 * RB) + align16(sizeof(T) * 64));
     const int64_t aux = wave_aux_bytes(RB, sizeof(T));
-    const int64_t total = a.num_dev ? int64_t(*a.num_dev) : a.num;
+    const int64_t total = a.num_dev ? int64_t(a.id_base) + *a.num_dev : a.num;
     // Work items: blockIdx.x and blockIdx.x + G first, then 2G + the queue
     // counter; the next item is always known one LP ahead, so its data can be
     // in flight while the current LP pivots.
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
         const int64_t need = aux + int64_t(P.C) * P.ldm * int64_t(sizeof(T));
         const bool fits = P.C <= 64 && m <= 64 * RB && need <= a.lds_bytes;
         if (!fits && lane == 0) {
-            const int slot = atomicAdd(a.defer_count, 1);
+            const int slot = a.defer_base + atomicAdd(a.defer_count, 1);
             a.defer_ids[slot] = int32_t(k);
         }
         const int N = P.N, C = P.C, ldm = P.ldm;
@@ -562,12 +562,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
             if (a.enter_out) a.enter_out[k] = (status == kUnbounded) ? enter : -1;
             if (a.stats) {
                 int32_t *st = a.stats + 8 * k;
-                st[0] = P.it1;
-                st[1] = P.iters - P.it1;
-                st[2] = P.degp;
-                st[3] = 0;
-                st[4] = 0;
-                st[5] = 0;
+                if (a.refine_stats) {
+                    st[3] = 1;
+                    st[4] = P.iters;
+                } else {
+                    st[0] = P.it1;
+                    st[1] = P.iters - P.it1;
+                    st[2] = P.degp;
+                    st[3] = 0;
+                    st[4] = 0;
+                    st[5] = 0;
+                }
                 st[6] = 1;
                 st[7] = nbs;
             }
@@ -582,6 +587,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
         cur = nxt;
         nxt = lane_get(pend, 0);
     }
+    if (lane == 0) finish_launch(a.queue, a.done, a.reset_extra);
 }
 
 template <typename T, int RB>

@@ -184,3 +184,60 @@ def test_synchronous_entry_point():
     sol = lpbatch.batch_solve(lpbatch.DeviceBatch.from_host(bt))
     ref = oracle_solve(bt)
     assert_parity(bt, sol.status.cpu().numpy(), sol.obj.cpu().numpy(), sol.x.cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------- FP32 tableau + FP64 certificate
+
+FP32 = dict(precision=1)
+
+
+def check_fp32(ctx, batch, rtol=1e-9):
+    """Single-precision pivots, then the FP64 certificate / re-solve: results
+    carry FP64 accuracy (the bar for this path is 1e-4 relative; it is held to
+    1e-9 here)."""
+    st, obj, x, stats = run(ctx, batch, **FP32)
+    ref = oracle_solve(batch)
+    assert_parity(batch, st, obj, x, ref, rtol=rtol)
+    return st, obj, x, stats, ref
+
+
+def test_fp32_certified_uniform_50x50(ctx):
+    st, obj, x, stats, ref = check_fp32(ctx, W.config1(5000))
+    cert = stats[:, 5]
+    assert np.mean((cert & 3) == 3) > 0.95  # most bases certified without a re-solve
+
+
+def test_fp32_certified_two_phase_and_uneven(ctx):
+    check_fp32(ctx, W.phase1_batch(1500, 20, 15, seed=32))
+    bt = W.uneven_batch(200, seed=1002)
+    st, obj, x, stats, ref = check_fp32(ctx, bt)
+    assert np.any((stats[:, 5] & 4) != 0)   # unbounded rays certified in FP64
+    assert np.any(stats[:, 3] == 1)          # infeasible LPs went to the FP64 re-solve
+
+
+def test_fp32_certified_support_and_large(ctx):
+    P, bt = W.config3(2000)
+    check_fp32(ctx, bt)
+    check_fp32(ctx, W.config4(8))
+
+
+def test_fp32_edge_cases(ctx):
+    lps = [
+        (np.array([[1.0, 1], [1, 3], [1, 0]]), [4, 6, 3.5], [2, 3], [0, 0, 0]),
+        (np.array([[1.0, 1], [1, 1], [0, 1]]), [2, 4, 3], [1, 2], [1, 0, 0]),
+        (np.array([[1.0, -1], [-1, 1]]), [1, 2], [1, 1], [0, 0]),
+        (np.array([[1.0, 1]]), [-1], [1, 0], [0]),
+        (np.array([[0.5, -5.5, -2.5, 9.0], [0.5, -1.5, -0.5, 1.0], [1.0, 0, 0, 0]]), [0, 0, 1],
+         [10, -57, -9, -24], [0, 0, 0]),
+        (np.array([[1.0, 1], [1, 1]]), [2, 2], [1, 1], [2, 2]),
+        (np.array([[1.0, np.nan]]), [1], [1, 1], [0]),
+        (np.array([[3.0, 1.0]]), [6], [-1.0, -2.0], [0]),   # optimum at the origin (no basic structural)
+    ]
+    bt = W.Batch(np.concatenate([np.asarray(a, float).ravel() for a, *_ in lps]),
+                 np.concatenate([np.asarray(b, float) for _, b, *_ in lps]),
+                 np.concatenate([np.asarray(c, float) for _, _, c, _ in lps]),
+                 np.concatenate([np.asarray(s, np.int8) for *_, s in lps]),
+                 np.array([np.asarray(a).shape[0] for a, *_ in lps], np.int32),
+                 np.array([np.asarray(a).shape[1] for a, *_ in lps], np.int32), "edge32")
+    st, obj, x, stats, ref = check_fp32(ctx, bt)
+    assert st[6] == oracle.INVALID_INPUT
