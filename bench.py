@@ -126,7 +126,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"],
+                    help="fp64: FP64 tableau; fp32c: FP32 tableau + FP64 certificate / re-solve")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
@@ -148,10 +149,11 @@ def main():
     ctx = lpbatch.Context(0)
     stream = torch.cuda.current_stream()
     N = batch.num_lps
-    out = ctx.solve(db, stats=True, stream=stream)  # allocates outputs once
+    prec = lpbatch.PREC_FP64 if args.precision == "fp64" else lpbatch.PREC_FP32_CERT64
+    out = ctx.solve(db, stats=True, stream=stream, precision=prec)  # allocates outputs once
     torch.cuda.synchronize()
     for _ in range(args.warmup):
-        ctx.solve(db, stats=True, stream=stream, out=out)
+        ctx.solve(db, stats=True, stream=stream, out=out, precision=prec)
     torch.cuda.synchronize()
 
     ctx.kernel_times()  # forget warm-up timings
@@ -160,7 +162,7 @@ def main():
     t_wall = time.perf_counter()
     start.record(stream)
     for _ in range(args.steps):
-        ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True)
+        ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True, precision=prec)
     stop.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
@@ -175,7 +177,7 @@ def main():
     stats = out.stats.cpu().numpy()
     status = out.status.cpu().numpy()
     obj = out.obj.cpu().numpy()
-    tab_bytes, hbm_bytes, mean_piv = algorithmic_bytes(batch, stats, 8)
+    tab_bytes, hbm_bytes, mean_piv = algorithmic_bytes(batch, stats, 8 if args.precision == "fp64" else 4)
     dom_s = per_kernel[dom] * 1e-3
     lds_resident = bool(np.all(stats[:, 6] == 1))
     if lds_resident:
@@ -192,7 +194,8 @@ def main():
 
     rec = dict(metric=METRIC, value=N / (ms_per_step * 1e-3), unit="LPs/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step,
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64" if args.precision == "fp64" else "f32+f64",
                data="synthetic",
                config=dict(workload=batch.name, num_lps=N, m=int(batch.m.max()),
                            n=int(batch.n.max()), precision=args.precision,
@@ -206,6 +209,9 @@ def main():
         rel = np.abs(obj[:k][opt] - ref.obj[opt]) / np.maximum(1.0, np.abs(ref.obj[opt]))
         rec["parity"] = dict(compared=int(k), status_match=int(np.sum(status[:k] == ref.status)),
                              max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
+    if args.precision == "fp32c":
+        rec["certificate"] = dict(certified=int(np.sum((stats[:, 5] & 3) == 3) + np.sum((stats[:, 5] & 4) != 0)),
+                                  resolved_fp64=int(np.sum(stats[:, 3] == 1)))
     print(json.dumps(rec), flush=True)
     ctx.close()
     return 0

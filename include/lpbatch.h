@@ -90,8 +90,9 @@ typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32_CERT64 = 1 } lp_precision;
 #define LP_CERT_RAY_OK 4
 #define LP_CERT_SINGULAR 8
 
-#define LP_PLACE_LDS 1
-#define LP_PLACE_HBM 2
+#define LP_PLACE_LDS 1    /* tableau in LDS (stats: one wavefront per LP)    */
+#define LP_PLACE_HBM 2    /* tableau in a device-memory slot (workgroup)     */
+#define LP_PLACE_LDS_WG 3 /* stats only: tableau in LDS, one workgroup per LP */
 
 /*
  * lp_batch_solve -- solve a batch in FP64 on the current device, synchronously.

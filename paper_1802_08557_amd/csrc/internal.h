@@ -93,6 +93,8 @@ hipError_t simplex_configure(int max_lds);
 hipError_t launch_simplex_wave(bool fp32, int rb, const SolveArgs &a, int grid, hipStream_t s);
 int simplex_wave_blocks_per_cu(bool fp32, int rb, int lds_bytes);
 int64_t wave_lds_aux_bytes(int rb, bool fp32);
+// LDS bytes of a column-major wavefront tableau with m rows and `cols` columns.
+int64_t wave_tab_bytes(int m, int cols, bool fp32);
 hipError_t simplex_wave_configure(int max_lds);
 
 // Size of the LDS control block + index arrays + pivot row/column buffers for an

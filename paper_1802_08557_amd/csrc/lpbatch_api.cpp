@@ -166,9 +166,8 @@ struct PassCounters {
 
 bool wave_fit(const lp_ctx *ctx, int64_t mk, int64_t nk, bool fp32)
 {
-    const int64_t ts = fp32 ? 4 : 8;
     return nk <= 63 && mk <= 128 &&
-           lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, fp32) + mk * lpb::tableau_ld(int(nk) + 1) * ts <=
+           lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, fp32) + lpb::wave_tab_bytes(int(mk), int(nk) + 1, fp32) <=
                ctx->max_lds;
 }
 
@@ -196,7 +195,8 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
         w.defer_ids = defer_ids;
         w.defer_count = pc.defer;
         w.defer_base = int32_t(n_block);
-        const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) + int64_t(wm_max) * lpb::tableau_ld(wn_max + 1) * ts;
+        // Budget for the common case of no surplus columns; an LP needing more is deferred.
+        const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) + lpb::wave_tab_bytes(wm_max, wn_max + 1, fp32);
         w.lds_bytes = int32_t(lds);
         const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
         if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         const bool in_lds = !a.force_hbm && L.tab + tab_bytes <= int64_t(a.lds_bytes);
         if (in_lds) {
             P.tab = reinterpret_cast<T *>(smem + L.tab);
-            solve_lp<T, NT>(P, a, 1);
+            solve_lp<T, NT>(P, a, 3);
         } else {
             P.tab = reinterpret_cast<T *>(a.scratch + int64_t(blockIdx.x) * a.slot_bytes);
             solve_lp<T, NT>(P, a, 2);

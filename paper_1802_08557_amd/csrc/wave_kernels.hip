@@ -611,6 +611,11 @@ int occ_t(int lds)
 
 int64_t wave_lds_aux_bytes(int rb, bool fp32) { return wave_aux_bytes(rb, fp32 ? 4 : 8); }
 
+int64_t wave_tab_bytes(int m, int cols, bool fp32)
+{
+    return fp32 ? int64_t(cols) * col_stride<float>(m) * 4 : int64_t(cols) * col_stride<double>(m) * 8;
+}
+
 hipError_t launch_simplex_wave(bool fp32, int rb, const SolveArgs &a, int grid, hipStream_t s)
 {
     if (rb == 1) return fp32 ? launch_t<float, 1>(a, grid, s) : launch_t<double, 1>(a, grid, s);

@@ -48,6 +48,7 @@ def test_uniform_5x5_full(ctx):
 
 def test_uniform_50x50_reduced(ctx):
     st, obj, x, stats, ref = check(ctx, W.config1(4000))
+    assert np.all(stats[:, 6] == 1)  # every LP solved by the one-wavefront kernel
     # Same pricing and ratio rules as the oracle: the pivot counts agree
     # except where rounding separates a near-tie.
     same = np.mean(stats[:, 1] == ref.stats[:, 1])
@@ -84,6 +85,7 @@ def test_support_function_batch(ctx):
     P, bt = W.config3(3000)
     st, obj, x, stats, ref = check(ctx, bt)
     assert np.all(st == 0)
+    assert np.all(stats[:, 6] == 1)
 
 
 RAGGED = [1, 2, 63, 64, 65, 127, 128, 129, 200]
@@ -203,6 +205,7 @@ def check_fp32(ctx, batch, rtol=1e-9):
 
 def test_fp32_certified_uniform_50x50(ctx):
     st, obj, x, stats, ref = check_fp32(ctx, W.config1(5000))
+    assert np.all(stats[(stats[:, 3] == 0), 6] == 1)  # FP32 solves ran one wavefront per LP
     cert = stats[:, 5]
     assert np.mean((cert & 3) == 3) > 0.95  # most bases certified without a re-solve
 
@@ -217,7 +220,8 @@ def test_fp32_certified_two_phase_and_uneven(ctx):
 
 def test_fp32_certified_support_and_large(ctx):
     P, bt = W.config3(2000)
-    check_fp32(ctx, bt)
+    st, obj, x, stats, ref = check_fp32(ctx, bt)
+    assert np.all(stats[(stats[:, 3] == 0), 6] == 1)
     check_fp32(ctx, W.config4(8))
 
 
