@@ -225,8 +225,8 @@ def support_batch(P: Polytope, dirs: np.ndarray) -> Batch:
     A1, b1 = split_form(P)
     N = dirs.shape[0]
     m, n = A1.shape
-    A = np.broadcast_to(A1, (N, m, n)).reshape(-1).copy()
-    b = np.broadcast_to(b1, (N, m)).reshape(-1).copy()
+    A = np.tile(A1.reshape(-1), N)
+    b = np.tile(b1, N)
     c = np.concatenate([dirs, -dirs], axis=1).reshape(-1)
     return Batch(A, b, c, np.zeros(N * m, np.int8), np.full(N, m, np.int32),
                  np.full(N, n, np.int32), f"support_{m}x{n}_x{N}", dict(shared_A=True))
