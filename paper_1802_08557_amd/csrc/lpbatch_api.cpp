@@ -472,10 +472,12 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         const lpb::SolveParams p64 = fill_params(opts, false);
         ca.tol_feas = p64.tol_feas;
         ca.tol_opt = p64.tol_opt;
+        // One wavefront per LP; LU blocks up to 32 x 32 in LDS, larger ones in the
+        // workgroup's device-memory slot (decided per LP by the kernel).
         const int kmax = std::min(P.m_max, P.n_max);
-        const int cnt_nt = kmax <= 32 ? 64 : 256;
-        int64_t clds = lpb::certify_lds_bytes(P.m_max, P.n_max, true);
-        if (clds > std::min<int64_t>(ctx->max_lds, 64 * 1024)) clds = lpb::certify_lds_bytes(P.m_max, P.n_max, false);
+        const int cnt_nt = 64;
+        const int64_t kl = std::min(kmax, 32);
+        const int64_t clds = lpb::certify_lds_bytes(P.m_max, P.n_max, false) + 8 * kl * kl;
         if (clds > ctx->max_lds) return fail(LP_ERR_ARG, "LP too large for the certificate kernel");
         ca.lds_bytes = int32_t(clds);
         const int per_cu = lpb::certify_blocks_per_cu(cnt_nt, int(clds));
