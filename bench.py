@@ -45,18 +45,21 @@ def workload(cfg):
 
 
 def algorithmic_bytes(batch, stats, tsize):
-    """Per-launch algorithmic bytes.
-    LDS/tableau: s*(m+1)*(N+1) to build the condensed tableau plus, per pivot,
-    one read and one write of it, 2*s*(m+1)*(N+1) (N = n non-basic columns for
-    all-<= rows).  HBM: the inputs A, b, c, sense read once and x, obj, status,
-    stats written once."""
+    """Per-launch algorithmic bytes, split by where each LP's tableau lived.
+    Tableau: s*(m+1)*(N+1) to build the condensed tableau plus, per pivot, one
+    read and one write of it, 2*s*(m+1)*(N+1) (N = n non-basic columns for
+    all-<= rows) -- LDS traffic for LDS-resident tableaux (placement 1 or 3),
+    HBM traffic for tableaux in device-memory slots (placement 2).  HBM also
+    carries the inputs A, b, c, sense read once and x, obj, status, stats
+    written once.  Returns (lds_bytes, hbm_bytes, io_bytes, mean pivots)."""
     m = batch.m.astype(np.float64)
     n = batch.n.astype(np.float64)
     pivots = stats[:, 0].astype(np.float64) + stats[:, 1]
     cells = (m + 1) * (n + 1)
-    tab = float(np.sum(tsize * cells * (1.0 + 2.0 * pivots)))
-    hbm = float(np.sum(8 * (m * n + m + n) + m + 8 * n + 8 + 4 + 4 * 8))
-    return tab, hbm, float(pivots.mean())
+    tab = tsize * cells * (1.0 + 2.0 * pivots)
+    in_hbm = stats[:, 6] == 2
+    io = float(np.sum(8 * (m * n + m + n) + m + 8 * n + 8 + 4 + 4 * 8))
+    return float(tab[~in_hbm].sum()), float(tab[in_hbm].sum()) + io, io, float(pivots.mean())
 
 
 def cpu_baseline(batch, max_lps=100_000):
@@ -120,6 +123,113 @@ def copy_calibration(gib):
     return 0
 
 
+def support_labels(P, dirs, chunk=20_000):
+    """Oracle-solved tight-constraint labels of the split-form support LPs."""
+    import oracle
+    from oracle import mlp
+    from paper_1802_08557_amd import workloads as W
+    A1, b1 = W.split_form(P)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    Y = np.empty((dirs.shape[0], A1.shape[0]), np.uint8)
+    for lo in range(0, dirs.shape[0], chunk):
+        bt = W.support_batch(P, dirs[lo:lo + chunk])
+        r = oracle.solve(bt.A, bt.b, bt.c, bt.sense, bt.m, bt.n, threads=threads)
+        Y[lo:lo + chunk] = mlp.tight_mask(A1, b1, r.x.reshape(-1, A1.shape[1]))
+    return Y
+
+
+def warm_start_block(args):
+    """Support-function batch (1e5 directions over one 120 x 40 polytope):
+    plain FP64, plain FP32 + certificate, and the network-screened FP32 +
+    certificate solve with a trained and with an untrained network.  Every
+    mode is checked against the oracle on a sample; times are per 1e5 LPs."""
+    import torch
+    import oracle
+    from paper_1802_08557_amd import lpbatch, warmstart
+    from paper_1802_08557_amd import workloads as W
+    t0 = time.perf_counter()
+    P = W.polytope(1003)
+    A1, b1 = W.split_form(P)
+    s1 = np.zeros(A1.shape[0], np.int8)
+    dirs = W.directions(args.warm_lps, 1103)
+    c = np.concatenate([dirs, -dirs], axis=1)
+    train_dirs = W.directions(args.warm_train, 1203)
+    Y = support_labels(P, train_dirs)
+    label_s = time.perf_counter() - t0
+    db = lpbatch.DeviceBatch.shared_from_host(A1, b1, s1, c)
+    d_eval = torch.from_numpy(dirs.astype(np.float32)).cuda()
+    d_train = torch.from_numpy(train_dirs.astype(np.float32)).cuda()
+    y_train = torch.from_numpy(Y).cuda()
+    ctx = lpbatch.Context(0)
+    t1 = time.perf_counter()
+    ctx.mlp_init(7)
+    losses = warmstart.train(ctx, d_train, y_train, epochs=args.warm_epochs, seed=11)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    cold = lpbatch.Context(0)
+    cold.mlp_init(7)
+    stream = torch.cuda.current_stream()
+    N = c.shape[0]
+
+    def timed(fn, steps):
+        out = fn(None)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            fn(out)
+        torch.cuda.synchronize()
+        for cx in (ctx, cold):
+            cx.kernel_times()
+        st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record(stream)
+        for _ in range(steps):
+            fn(out, timing=True)
+        sp.record(stream)
+        torch.cuda.synchronize()
+        per_kernel = {}
+        for cx in (ctx, cold):
+            for nm, v in cx.kernel_times():
+                per_kernel.setdefault(nm, []).append(v)
+        return out, st.elapsed_time(sp) / steps, {k: float(np.sum(v)) / steps for k, v in per_kernel.items()}
+
+    K = args.warm_k
+    modes = {
+        "plain_fp64": lambda out, timing=False: ctx.solve(db, stats=True, out=out, stream=stream,
+                                                            time_kernels=timing),
+        "plain_fp32_cert": lambda out, timing=False: ctx.solve(db, stats=True, out=out, stream=stream,
+                                                                 precision=lpbatch.PREC_FP32_CERT64,
+                                                                 time_kernels=timing),
+        "warm_fp32_cert": lambda out, timing=False: warmstart.warm_solve(
+            ctx, db, d_eval, K, stats=True, out=out, stream=stream, time_kernels=timing),
+        "untrained_fp32_cert": lambda out, timing=False: warmstart.warm_solve(
+            cold, db, d_eval, K, stats=True, out=out, stream=stream, time_kernels=timing),
+    }
+    # Oracle on a sample of the evaluation directions (all modes are compared with it).
+    ns = min(N, args.warm_sample)
+    bt = W.support_batch(P, dirs[:ns])
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    ref = oracle.solve(bt.A, bt.b, bt.c, bt.sense, bt.m, bt.n, threads=threads)
+    res = {}
+    for name, fn in modes.items():
+        out, ms, kern = timed(fn, args.warm_steps)
+        stn = out.status.cpu().numpy()
+        obj = out.obj.cpu().numpy()
+        stats = out.stats.cpu().numpy()
+        opt = ref.status == 0
+        rel = np.abs(obj[:ns][opt] - ref.obj[opt]) / np.maximum(1.0, np.abs(ref.obj[opt]))
+        res[name] = dict(lps_per_s=N / (ms * 1e-3), ms_per_step=ms, kernels_ms=kern,
+                         resolved_fp64=int(np.sum(stats[:, 3] == 1)),
+                         status_match=int(np.sum(stn[:ns] == ref.status)), compared=int(ns),
+                         max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
+    base = res["plain_fp64"]["lps_per_s"]
+    for name in res:
+        res[name]["speedup_vs_plain_fp64"] = res[name]["lps_per_s"] / base
+    ctx.close()
+    cold.close()
+    return dict(workload=f"support_120x40_x{N}", screened_rows=K, train_lps=int(args.warm_train),
+                epochs=int(args.warm_epochs), label_s=label_s, train_s=train_s,
+                final_loss=losses[-1] if losses else None, modes=res)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +241,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start comparison")
+    ap.add_argument("--warm-only", action="store_true", help="print only the warm-start comparison")
+    ap.add_argument("--warm-lps", type=int, default=100_000)
+    ap.add_argument("--warm-train", type=int, default=200_000)
+    ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--warm-k", type=int, default=56)
+    ap.add_argument("--warm-steps", type=int, default=10)
+    ap.add_argument("--warm-sample", type=int, default=20_000)
     args = ap.parse_args()
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
@@ -143,6 +261,9 @@ def main():
     import torch
     from paper_1802_08557_amd import lpbatch
     from paper_1802_08557_amd.lpbatch import DeviceBatch
+    if args.warm_only:
+        print(json.dumps(warm_start_block(args)), flush=True)
+        return 0
 
     batch = workload(args.config)
     db = DeviceBatch.from_host(batch)
@@ -177,20 +298,25 @@ def main():
     stats = out.stats.cpu().numpy()
     status = out.status.cpu().numpy()
     obj = out.obj.cpu().numpy()
-    tab_bytes, hbm_bytes, mean_piv = algorithmic_bytes(batch, stats, 8 if args.precision == "fp64" else 4)
+    lds_bytes, hbm_bytes, io_bytes, mean_piv = algorithmic_bytes(
+        batch, stats, 8 if args.precision == "fp64" else 4)
+    # Roofline of the solve kernels: the time the busier memory tier needs for
+    # the algorithmic bytes, T = max(LDS bytes / LDS peak, HBM bytes / HBM peak),
+    # against the measured time of the dominant kernel.
     dom_s = per_kernel[dom] * 1e-3
-    lds_resident = bool(np.all(stats[:, 6] == 1))
-    if lds_resident:
-        roof = dict(bound="lds", achieved=tab_bytes / dom_s / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s",
-                    frac=tab_bytes / dom_s / PEAK_LDS, traffic=None)
+    t_lds, t_hbm = lds_bytes / PEAK_LDS, hbm_bytes / PEAK_HBM
+    if t_lds >= t_hbm:
+        roof = dict(bound="lds", achieved=lds_bytes / dom_s / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s",
+                    frac=lds_bytes / dom_s / PEAK_LDS, traffic=None)
     else:
-        roof = dict(bound="hbm", achieved=(tab_bytes + hbm_bytes) / dom_s / 1e9,
-                    peak=PEAK_HBM / 1e9, unit="GB/s",
-                    frac=(tab_bytes + hbm_bytes) / dom_s / PEAK_HBM, traffic=None)
+        roof = dict(bound="hbm", achieved=hbm_bytes / dom_s / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                    frac=hbm_bytes / dom_s / PEAK_HBM, traffic=None)
     roof["traffic"] = measured_traffic(dom, batch.name)
-    roof.update(kernel=dom, kernel_ms=per_kernel[dom], hbm_bytes_alg=hbm_bytes,
-                hbm_frac=hbm_bytes / dom_s / PEAK_HBM, tableau_bytes_alg=tab_bytes,
-                mean_pivots=mean_piv)
+    roof.update(kernel=dom, kernel_ms=per_kernel[dom], lds_bytes_alg=lds_bytes, hbm_bytes_alg=hbm_bytes,
+                io_bytes_alg=io_bytes, lds_frac=lds_bytes / dom_s / PEAK_LDS,
+                hbm_frac=hbm_bytes / dom_s / PEAK_HBM, mean_pivots=mean_piv,
+                placement_counts={str(p): int(np.sum(stats[:, 6] == p)) for p in (1, 2, 3)})
+    lds_resident = bool(np.all(stats[:, 6] != 2))
 
     rec = dict(metric=METRIC, value=N / (ms_per_step * 1e-3), unit="LPs/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step,
@@ -209,6 +335,11 @@ def main():
         rel = np.abs(obj[:k][opt] - ref.obj[opt]) / np.maximum(1.0, np.abs(ref.obj[opt]))
         rec["parity"] = dict(compared=int(k), status_match=int(np.sum(status[:k] == ref.status)),
                              max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
+    if not args.no_warm and args.config == 1:
+        try:
+            rec["warm_start"] = warm_start_block(args)
+        except Exception as e:  # the main measurement stands on its own
+            rec["warm_start"] = dict(error=f"{type(e).__name__}: {e}")
     if args.precision == "fp32c":
         rec["certificate"] = dict(certified=int(np.sum((stats[:, 5] & 3) == 3) + np.sum((stats[:, 5] & 4) != 0)),
                                   resolved_fp64=int(np.sum(stats[:, 3] == 1)))

@@ -132,10 +132,37 @@ typedef struct {
     int32_t *stats;      /* optional DEVICE int32 [num_lps][LP_STATS_WIDTH]       */
     void *stream;        /* hipStream_t the work is queued on; NULL: null stream  */
     uint32_t flags;      /* LP_FLAG_*                                              */
+    /* Shared constraints (the support-function workload of the paper's
+     * "Motivating Application" section: one polytope, many objectives).
+     * shared = 1: A, b and sense hold ONE LP of m[0] x n[0] that every LP of
+     * the batch uses; c, x, status and obj stay per LP; every m[k] must equal
+     * m[0] and every n[k] n[0].                                                 */
+    int32_t shared;
+    /* Screened solve (needs shared = 1): a DEVICE int32 [num_lps][subset_m]
+     * list of constraint indices.  LP k is first solved on those rows only --
+     * a relaxation, since dropping constraints only enlarges the feasible
+     * set -- in the chosen precision.  Its final basis, completed with the
+     * slacks of the omitted rows, is then certified in FP64 against EVERY
+     * row (primal feasibility of all m rows, reduced costs); an LP whose
+     * relaxation is not optimal or whose basis fails is re-solved on all rows
+     * in FP64 from the slack basis (stats[LP_STAT_FALLBACK] = 1).  Results
+     * always refer to the full LP.  An index outside 0..m[0]-1 makes that LP
+     * LP_INVALID_INPUT in the first pass and sends it to the re-solve.       */
+    const int32_t *row_subset;
+    int32_t subset_m;    /* rows per LP in row_subset, 1..m[0]                    */
 } lp_options;
 
 #define LP_FLAG_SYNC 1u        /* wait for the stream before returning            */
 #define LP_FLAG_TIME_KERNELS 2u /* record HIP events around each kernel launched  */
+/* Uneven batches: LPs the one-wavefront kernel cannot take are grouped in
+ * size bins by tableau cells ((m+1)(n+1) <= 64^2, 128^2, 256^2, larger), each
+ * bin one persistent launch of the workgroup kernel whose queue hands out the
+ * most expensive LPs first.  With LP_FLAG_AUTOTUNE, every bin not yet in the
+ * context's table is first timed on a sample of up to 256 of its LPs for each
+ * workgroup size (64, 128, 256, 512) and placement (LDS when it fits, or
+ * device memory), and the fastest is kept in the context for later calls.
+ * The call is then synchronous; results are as without the flag. */
+#define LP_FLAG_AUTOTUNE 4u
 
 void lp_options_init(lp_options *opts);
 
@@ -162,6 +189,84 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
  * LP_ERR_* code.
  */
 int lp_ctx_kernel_times(lp_ctx *ctx, const char **names, float *ms, int cap);
+
+/*
+ * lp_ctx_tuning -- the context's autotuned launches, up to `cap` entries of
+ * 4 int32 each (HOST memory): size bin (0..3), 1 for FP32 tableaux, workgroup
+ * size, 1 when tableaux go to device memory.  Returns the number of entries
+ * the table holds (entries may be NULL to count), or a negative LP_ERR_* code.
+ */
+int lp_ctx_tuning(lp_ctx *ctx, int32_t *entries, int cap);
+
+/*
+ * lp_hyperbox_support -- LPs whose feasible set is a hyper-rectangle, in
+ * closed form (paper, "Solving a Special Case of LP", Eq. (7)):
+ *
+ *   value[k] = max { l_k . x : lo_k <= x <= hi_k } = sum_i l_ki h_ki,
+ *   h_ki = lo_ki if l_ki < 0, else hi_ki   (l_ki = 0 takes hi_ki),
+ *
+ * summed in index order.  l is [num][n]; lo and hi are [num][n], or [n] for
+ * one box shared by every direction when shared_box = 1; value is [num]; x
+ * (optional, NULL to skip) receives the maximiser h, [num][n].  All DEVICE
+ * pointers, row-major; lo <= hi is the caller's to ensure.  Queued on stream
+ * (NULL: null stream).  Returns LP_OK or a negative LP_ERR_* code.
+ */
+int lp_hyperbox_support(lp_ctx *ctx, int64_t num, int32_t n, const double *lo, const double *hi,
+                        const double *l, int32_t shared_box, double *value, double *x, void *stream);
+
+/*
+ * Warm-start scoring network.
+ *
+ * For many LPs that share one constraint set and differ only in the objective
+ * -- the support-function queries max l^T x over a fixed polytope that the
+ * paper's "Motivating Application" section solves in bulk -- a small network
+ * maps the direction l to one score per constraint; high scores mark the
+ * constraints expected to be tight at the optimum.  The scores choose the rows
+ * of the relaxed LP that lp_options.row_subset solves first.  The paper has no
+ * learned component; this is an addition around its method.
+ *
+ * Architecture 20 -> 256 -> 256 -> 120 with ReLU.  Parameters are one FP32
+ * vector of LP_MLP_NUM_PARAMS values in the order W1 [256][20], b1 [256],
+ * W2 [256][256], b2 [256], W3 [120][256], b3 [120] (row-major, output index
+ * first).  Matrix products take BF16 operands (weights, inputs and hidden
+ * activations rounded to nearest-even) and accumulate in FP32 on the matrix
+ * cores; biases, scores and gradients are FP32.  Training minimises the mean
+ * binary cross-entropy with logits over all B x 120 outputs with AdamW
+ * (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay on W1, W2, W3).
+ *
+ * The network lives in the context.  Every pointer argument except `path` is
+ * a DEVICE pointer; work is queued on `stream` (NULL: null stream) and the
+ * context's buffers are reused by the next call, so calls on one context must
+ * be ordered on one stream.  Returns LP_OK or a negative LP_ERR_* code.
+ */
+#define LP_MLP_IN 20
+#define LP_MLP_HIDDEN 256
+#define LP_MLP_OUT 120
+#define LP_MLP_NUM_PARAMS 102008
+
+/* Fresh parameters: weights uniform in +-sqrt(6 / fan_in) from a splitmix64
+ * stream seeded by `seed`, zero biases; clears the AdamW state.  Synchronous. */
+int lp_mlp_init(lp_ctx *ctx, uint64_t seed);
+/* Copies LP_MLP_NUM_PARAMS FP32 parameters in (clears the AdamW state) or out. */
+int lp_mlp_set_params(lp_ctx *ctx, const float *params, void *stream);
+int lp_mlp_get_params(lp_ctx *ctx, float *params, void *stream);
+/* Scores of B directions dirs [B][20] (FP32): scores [B][120] (optional) and
+ * top_k [B][k] (optional, 1 <= k <= 120): the indices of the k highest scores
+ * of each row, highest first, equal scores lower index first. */
+int lp_mlp_infer(lp_ctx *ctx, int64_t B, const float *dirs, float *scores, int32_t *top_k,
+                 int32_t k, void *stream);
+/* Gradient of the loss on B labelled rows (tight [B][120]: 1 = tight) into
+ * grad_out [LP_MLP_NUM_PARAMS] and the loss into loss_out[0] (either optional);
+ * the parameters are not changed. */
+int lp_mlp_grads(lp_ctx *ctx, int64_t B, const float *dirs, const uint8_t *tight,
+                 float *grad_out, float *loss_out, void *stream);
+/* One AdamW step on B labelled rows; the loss before the step goes to
+ * loss_out[0] (optional). */
+int lp_mlp_train_step(lp_ctx *ctx, int64_t B, const float *dirs, const uint8_t *tight,
+                      float lr, float weight_decay, float *loss_out, void *stream);
+/* Parameters and AdamW state to / from a file (host path); synchronous. */
+int lp_mlp_save(lp_ctx *ctx, const char *path);
+int lp_mlp_load(lp_ctx *ctx, const char *path);
 
 /* Text of the last failure on the calling thread ("" if none). */
 const char *lp_last_error(void);

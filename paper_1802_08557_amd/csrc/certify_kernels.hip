@@ -123,6 +123,20 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
         const double *A = a.A + ao, *b = a.b + ro, *c = a.c + co;
         const int8_t *sense = a.sense + ro;
         const int32_t *basis = a.basis + ro;
+        // Screened solve: the basis covers the ms rows sub[] of the shared LP
+        // (in that solve's numbering); every other row's slack is basic.
+        const int32_t *sub = nullptr;
+        int ms = m;
+        if (a.shared) {
+            A = a.A;
+            b = a.b;
+            sense = a.sense;
+            if (a.row_subset) {
+                ms = a.subset_m;
+                sub = a.row_subset + k * int64_t(ms);
+                basis = a.basis + k * int64_t(ms);
+            }
+        }
         double *x = a.x + co;
         const int st0 = a.status[k];
         // LDS carve-up for this LP.
@@ -143,7 +157,9 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                                 align16(8 * 3 * int64_t(kmax) + 4 * int64_t(kmax));
         int cert = 0;
         bool fallback = !(st0 == kOptimal || st0 == kUnbounded);
-        if (st0 == kInvalid) fallback = false;
+        // Invalid input stays invalid -- unless it was only the screening's row
+        // list that was bad: the re-solve on all rows then decides.
+        if (st0 == kInvalid) fallback = a.shared && a.row_subset;
         const bool work = st0 == kOptimal || st0 == kUnbounded;
 
         if (work) {
@@ -154,24 +170,44 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                 int sen = sense[i];
                 const bool neg = bi < 0.0;
                 if (neg && sen != kEQ) sen = (sen == kLE) ? kGE : kLE;
-                rowf[i] = (neg ? kRowNeg : 0) | (sen << 1) | kTight;
+                rowf[i] = (neg ? kRowNeg : 0) | (sen << 1) | (sub ? 0 : kTight);
             }
             for (int j = tid; j < n; j += NT) colf[j] = 0;
             __syncthreads();
-            for (int r = tid; r < m; r += NT) {
+            // Row of the full LP behind row r of the solve that made the basis.
+            auto full_row = [&](int r) -> int {
+                if (!sub) return r;
+                const int q = sub[r];
+                return (q >= 0 && q < m) ? q : -1;
+            };
+            if (sub) {
+                for (int r = tid; r < ms; r += NT) {
+                    const int q = full_row(r);
+                    if (q < 0) sh->fail = 9;
+                    else atomicOr(&rowf[q], kTight);
+                }
+                __syncthreads();
+            }
+            for (int r = tid; r < ms; r += NT) {
                 const int v = basis[r];
-                if (v < -1 || v >= n + 2 * m) {
+                if (v < -1 || v >= n + 2 * ms) {
                     sh->fail = 9;  // not a basis of this LP
                 } else if (v < 0) {
-                    atomicOr(&rowf[r], kDeadRow);
-                    atomicAnd(&rowf[r], ~kTight);
+                    const int q = full_row(r);
+                    if (q < 0) { sh->fail = 9; continue; }
+                    atomicOr(&rowf[q], kDeadRow);
+                    atomicAnd(&rowf[q], ~kTight);
                 } else if (v < n) {
                     colf[v] = kTight;
-                } else if (v < n + m) {
-                    atomicAnd(&rowf[v - n], ~kTight);
+                } else if (v < n + ms) {
+                    const int q = full_row(v - n);
+                    if (q < 0) { sh->fail = 9; continue; }
+                    atomicAnd(&rowf[q], ~kTight);
                 } else {
-                    atomicOr(&rowf[v - n - m], kDeadRow);
-                    atomicAnd(&rowf[v - n - m], ~kTight);
+                    const int q = full_row(v - n - ms);
+                    if (q < 0) { sh->fail = 9; continue; }
+                    atomicOr(&rowf[q], kDeadRow);
+                    atomicAnd(&rowf[q], ~kTight);
                 }
             }
             __syncthreads();
@@ -289,7 +325,7 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     for (int s2 = 0; s2 < K; ++s2) ax = fma(A[int64_t(i) * n + slist[s2]], xs[s2], ax);
                     const double r = sg * (b[i] - ax);  // normalised slack b_i - a_i x
                     const int sen = (f >> 1) & 3;
-                    if (f & kDeadRow) pf &= fabs(r) <= tol_p;
+                    if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;  // a row left out of a screened solve can be an equality
                     else if (sen == kLE) pf &= r >= -tol_p;
                     else if (sen == kGE) pf &= -r >= -tol_p;
                 }
@@ -322,7 +358,13 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     if (sh->fail == 0) cert |= LP_CERT_DUAL_OK_BIT;
                 } else if (st0 == kUnbounded && primal_ok) {
                     // Ray of the entering variable q.
-                    const int q = a.enter[k];
+                    int q = a.enter[k];
+                    if (sub && q >= n && q < n + ms) {
+                        const int fr = full_row(q - n);
+                        q = fr >= 0 ? n + fr : -1;
+                    } else if (sub && q >= n + ms) {
+                        q = -1;
+                    }
                     bool rf = q >= 0 && q < n + m && !(q < n && spos[q] >= 0);
                     int tr = -1;
                     double sq = 0.0;
@@ -372,7 +414,7 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                             for (int s2 = 0; s2 < K; ++s2) ad = fma(A[int64_t(i) * n + slist[s2]], -wv[s2], ad);
                             const double dr = -sg * ad;  // change of the normalised slack
                             const int sen = (f >> 1) & 3;
-                            if (f & kDeadRow) ok2 &= fabs(dr) <= tol_r;
+                            if ((f & kDeadRow) || sen == kEQ) ok2 &= fabs(dr) <= tol_r;
                             else if (sen == kLE) ok2 &= dr >= -tol_r;
                             else if (sen == kGE) ok2 &= -dr >= -tol_r;
                         }
@@ -425,6 +467,354 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
     if (tid == 0) finish_launch(a.queue, a.done, nullptr);
 }
 
+
+// Compiler-level ordering point for a wavefront's own LDS traffic: the
+// hardware keeps one wavefront's LDS accesses in program order, so a fence at
+// wavefront scope is all that keeps the compiler from reordering them.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+__device__ __forceinline__ bool wave_all(bool v) { return __ballot(!v) == 0; }
+
+// The same certificate with one wavefront per LP and no workgroup barrier:
+// lane t holds row t of the k x k block B_TS (column-major in LDS), the LU
+// picks each pivot by a wavefront max (ties to the lower lane) and records
+// the order instead of swapping rows; triangular solves broadcast one value
+// per step with readlane.  W wavefronts share a workgroup, each with its own
+// LP and LDS region; with stage_a the shared constraint matrix is copied into
+// LDS once per workgroup and every A access of the certificate hits LDS.
+template <int W>
+__global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t off = 0;
+    const double *Astage = nullptr;
+    if (a.stage_a) {
+        double *As = reinterpret_cast<double *>(smem);
+        const int64_t cnt = int64_t(a.um) * a.un;
+        for (int64_t e = threadIdx.x; e < cnt; e += 64 * W) As[e] = a.A[e];
+        __syncthreads();
+        Astage = As;
+        off = align16(8 * cnt);
+    }
+    char *my = smem + off + int64_t(wave) * a.wave_bytes;
+    const int64_t total = a.num;
+    int64_t item = int64_t(blockIdx.x) * W + wave;
+    while (item < total) {
+        int nxt = 0;
+        if (lane == 0) nxt = int(gridDim.x) * W + atomicAdd(a.queue, 1);
+        const int64_t k = item;
+        int m, n;
+        int64_t ao, ro, co;
+        if (a.um > 0) {
+            m = a.um; n = a.un; ao = k * int64_t(m) * n; ro = k * m; co = k * n;
+        } else {
+            m = a.m[k]; n = a.n[k]; ao = a.aoff[k]; ro = a.roff[k]; co = a.coff[k];
+        }
+        const double *A = a.A + ao, *b = a.b + ro, *c = a.c + co;
+        const int8_t *sense = a.sense + ro;
+        const int32_t *basis = a.basis + ro;
+        const int32_t *sub = nullptr;
+        int ms = m;
+        if (a.shared) {
+            A = Astage ? Astage : a.A;
+            b = a.b;
+            sense = a.sense;
+            if (a.row_subset) {
+                ms = a.subset_m;
+                sub = a.row_subset + k * int64_t(ms);
+                basis = a.basis + k * int64_t(ms);
+            }
+        }
+        double *x = a.x + co;
+        const int st0 = a.status[k];
+        const WaveCertLayout L = wave_cert_layout(m, n, a.kl);
+        int *rowf = reinterpret_cast<int *>(my + L.rowf);
+        int *tpos = reinterpret_cast<int *>(my + L.tpos);
+        int *colf = reinterpret_cast<int *>(my + L.colf);
+        int *spos = reinterpret_cast<int *>(my + L.spos);
+        int *tlist = reinterpret_cast<int *>(my + L.tlist);
+        int *slist = reinterpret_cast<int *>(my + L.slist);
+        int *order = reinterpret_cast<int *>(my + L.order);
+        double *xsv = reinterpret_cast<double *>(my + L.xs);
+        double *yv = reinterpret_cast<double *>(my + L.yv);
+        int cert = 0;
+        bool fallback = !(st0 == kOptimal || st0 == kUnbounded);
+        if (st0 == kInvalid) fallback = a.shared && a.row_subset;
+        const bool work = st0 == kOptimal || st0 == kUnbounded;
+
+        if (work) {
+            // Rows: sign normalisation and the tight set; columns: the basic set.
+            for (int i = lane; i < m; i += 64) {
+                const double bi = b[i];
+                int sen = sense[i];
+                const bool neg = bi < 0.0;
+                if (neg && sen != kEQ) sen = (sen == kLE) ? kGE : kLE;
+                rowf[i] = (neg ? kRowNeg : 0) | (sen << 1) | (sub ? 0 : kTight);
+            }
+            for (int j = lane; j < n; j += 64) colf[j] = 0;
+            wave_sync();
+            bool bad = false;
+            auto full_row = [&](int r) -> int {
+                if (!sub) return r;
+                const int q = sub[r];
+                return (q >= 0 && q < m) ? q : -1;
+            };
+            if (sub) {
+                for (int r = lane; r < ms; r += 64) {
+                    const int q = full_row(r);
+                    if (q < 0) bad = true;
+                    else atomicOr(&rowf[q], kTight);
+                }
+                wave_sync();
+            }
+            for (int r = lane; r < ms; r += 64) {
+                const int v = basis[r];
+                int q = -1;
+                if (v < -1 || v >= n + 2 * ms) {
+                    bad = true;
+                } else if (v < 0) {
+                    q = full_row(r);
+                    if (q < 0) bad = true;
+                    else { atomicOr(&rowf[q], kDeadRow); atomicAnd(&rowf[q], ~kTight); }
+                } else if (v < n) {
+                    colf[v] = kTight;
+                } else if (v < n + ms) {
+                    q = full_row(v - n);
+                    if (q < 0) bad = true;
+                    else atomicAnd(&rowf[q], ~kTight);
+                } else {
+                    q = full_row(v - n - ms);
+                    if (q < 0) bad = true;
+                    else { atomicOr(&rowf[q], kDeadRow); atomicAnd(&rowf[q], ~kTight); }
+                }
+            }
+            wave_sync();
+            const int kt = compact(rowf, kTight, m, tlist, tpos);
+            const int K = compact(colf, kTight, n, slist, spos);
+            wave_sync();
+            double bm = 0.0, cm = 0.0;
+            for (int i = lane; i < m; i += 64) bm = fmax(bm, fabs(b[i]));
+            for (int j = lane; j < n; j += 64) cm = fmax(cm, fabs(c[j]));
+            const double bnorm = wave_max(bm), cnorm = wave_max(cm);
+            const double tol_p = a.tol_feas * (1.0 + bnorm);
+            const double tol_d = a.tol_opt * fmax(1.0, cnorm);
+            bool ok = kt == K && K <= 64 && __ballot(bad) == 0;
+            double *M = (K <= a.kl) ? reinterpret_cast<double *>(my + L.mat)
+                                    : reinterpret_cast<double *>(a.scratch + (int64_t(blockIdx.x) * W + wave) *
+                                                                              a.slot_bytes);
+            // Lane t: row t of B_TS (column-major, M[s*K + t]) and its rhs; lane
+            // j: c of the j-th basic structural.
+            double rz = 0.0, cs = 0.0;
+            int pos = kBig;  // step at which this lane's row became the pivot row
+            if (ok) {
+                double am = 0.0;
+                if (lane < K) {
+                    const int i = tlist[lane];
+                    const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
+                    const double *Ai = A + int64_t(i) * n;
+                    for (int s2 = 0; s2 < K; ++s2) {
+                        const double v = sg * Ai[slist[s2]];
+                        M[s2 * K + lane] = v;
+                        am = fmax(am, fabs(v));
+                    }
+                    rz = sg * b[i];
+                    cs = c[slist[lane]];
+                }
+                const double amax = wave_max(am);
+                wave_sync();
+                for (int p = 0; p < K; ++p) {
+                    const double v = (lane < K && pos == kBig) ? fabs(M[p * K + lane]) : -1.0;
+                    const double vmax = wave_max(v);
+                    if (!(vmax > 1e-13 * fmax(1.0, amax))) { ok = false; break; }
+                    const int pl = __builtin_ctzll(__ballot(v == vmax));
+                    if (lane == pl) pos = p;
+                    if (lane == 0) order[p] = pl;
+                    const double u = M[p * K + pl];
+                    if (lane < K && pos == kBig) {
+                        const double l = M[p * K + lane] / u;
+                        M[p * K + lane] = l;
+                        for (int j = p + 1; j < K; ++j) M[j * K + lane] = fma(-l, M[j * K + pl], M[j * K + lane]);
+                    }
+                    wave_sync();
+                }
+                if (!ok) cert |= LP_CERT_SINGULAR_BIT;
+            }
+            double xr = 0.0;  // lane p: x of the p-th basic structural
+            if (ok) {
+                // x_S: L z = P b_T (lane-per-row), then U x = z.
+                for (int p = 0; p < K; ++p) {
+                    const double zp = lane_get(rz, order[p]);
+                    if (lane < K && pos > p) rz = fma(-M[p * K + lane], zp, rz);
+                }
+                for (int p = K - 1; p >= 0; --p) {
+                    const int pl = order[p];
+                    const double xp = lane_get(rz, pl) / M[p * K + pl];
+                    if (lane == p) xr = xp;
+                    if (lane < K && pos < p) rz = fma(-M[p * K + lane], xp, rz);
+                }
+                if (lane < K) xsv[lane] = xr;
+                // y_T: U^T w = c_S, L^T v = w (lane-per-position), y_t = v[pos_t].
+                double wr = 0.0;
+                for (int p = 0; p < K; ++p) {
+                    const int pl = order[p];
+                    const double wp = lane_get(cs, p) / M[p * K + pl];
+                    if (lane == p) wr = wp;
+                    if (lane > p && lane < K) cs = fma(-M[lane * K + pl], wp, cs);
+                }
+                for (int q = K - 1; q >= 0; --q) {
+                    const double vq = lane_get(wr, q);
+                    const int oq = order[q];
+                    if (lane < q) wr = fma(-M[lane * K + oq], vq, wr);
+                }
+                const double yt = __shfl(wr, pos < 64 ? pos : 0);
+                if (lane < K) yv[lane] = yt;
+                wave_sync();
+
+                // Primal certificate.
+                bool pf = !(lane < K) || xr >= -tol_p;
+                for (int i = lane; i < m; i += 64) {
+                    const int f = rowf[i];
+                    if (f & kTight) continue;
+                    const double *Ai = A + int64_t(i) * n;
+                    double ax0 = 0.0, ax1 = 0.0;
+                    int s2 = 0;
+                    for (; s2 + 1 < K; s2 += 2) {
+                        ax0 = fma(Ai[slist[s2]], xsv[s2], ax0);
+                        ax1 = fma(Ai[slist[s2 + 1]], xsv[s2 + 1], ax1);
+                    }
+                    if (s2 < K) ax0 = fma(Ai[slist[s2]], xsv[s2], ax0);
+                    const double sg = (f & kRowNeg) ? -1.0 : 1.0;
+                    const double r = sg * (b[i] - (ax0 + ax1));
+                    const int sen = (f >> 1) & 3;
+                    if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;  // a row left out of a screened solve can be an equality
+                    else if (sen == kLE) pf &= r >= -tol_p;
+                    else if (sen == kGE) pf &= -r >= -tol_p;
+                }
+                const bool primal_ok = wave_all(pf);
+                if (primal_ok) cert |= LP_CERT_PRIMAL_OK_BIT;
+
+                if (st0 == kOptimal && primal_ok) {
+                    // Dual certificate: reduced costs of every non-basic column.
+                    bool df = true;
+                    for (int j = lane; j < n; j += 64) {
+                        if (spos[j] >= 0) continue;
+                        double ya0 = 0.0, ya1 = 0.0;
+                        int t = 0;
+                        for (; t + 1 < K; t += 2) {
+                            const int i0 = tlist[t], i1 = tlist[t + 1];
+                            const double s0 = (rowf[i0] & kRowNeg) ? -1.0 : 1.0;
+                            const double s1 = (rowf[i1] & kRowNeg) ? -1.0 : 1.0;
+                            ya0 = fma(yv[t], s0 * A[int64_t(i0) * n + j], ya0);
+                            ya1 = fma(yv[t + 1], s1 * A[int64_t(i1) * n + j], ya1);
+                        }
+                        if (t < K) {
+                            const int i0 = tlist[t];
+                            const double s0 = (rowf[i0] & kRowNeg) ? -1.0 : 1.0;
+                            ya0 = fma(yv[t], s0 * A[int64_t(i0) * n + j], ya0);
+                        }
+                        df &= c[j] - (ya0 + ya1) <= tol_d;
+                    }
+                    if (lane < K) {
+                        const int sen = (rowf[tlist[lane]] >> 1) & 3;
+                        if (sen == kLE) df &= -yt <= tol_d;
+                        else if (sen == kGE) df &= yt <= tol_d;
+                    }
+                    if (wave_all(df)) cert |= LP_CERT_DUAL_OK_BIT;
+                } else if (st0 == kUnbounded && primal_ok) {
+                    // Ray of the entering variable q: w = B^-1 a_q, d_S = -w.
+                    int q = a.enter[k];
+                    if (sub && q >= n && q < n + ms) {
+                        const int fr = full_row(q - n);
+                        q = fr >= 0 ? n + fr : -1;
+                    } else if (sub && q >= n + ms) {
+                        q = -1;
+                    }
+                    bool rf = q >= 0 && q < n + m && !(q < n && spos[q] >= 0);
+                    int tr = -1;
+                    double sq = 0.0;
+                    if (rf && q >= n) {
+                        tr = tpos[q - n];
+                        const int sen = (rowf[q - n] >> 1) & 3;
+                        rf = tr >= 0 && sen != kEQ;
+                        sq = (sen == kLE) ? 1.0 : -1.0;
+                    }
+                    if (rf) {
+                        double rw = 0.0;
+                        if (lane < K) {
+                            const int i = tlist[lane];
+                            const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
+                            rw = (q < n) ? sg * A[int64_t(i) * n + q] : (lane == tr ? sq : 0.0);
+                        }
+                        for (int p = 0; p < K; ++p) {
+                            const double zp = lane_get(rw, order[p]);
+                            if (lane < K && pos > p) rw = fma(-M[p * K + lane], zp, rw);
+                        }
+                        double wd = 0.0;
+                        for (int p = K - 1; p >= 0; --p) {
+                            const int pl = order[p];
+                            const double xp = lane_get(rw, pl) / M[p * K + pl];
+                            if (lane == p) wd = xp;
+                            if (lane < K && pos < p) rw = fma(-M[p * K + lane], xp, rw);
+                        }
+                        const double tol_r = a.tol_feas;
+                        bool ok2 = !(lane < K) || -wd >= -tol_r;
+                        double gain = (lane < K) ? c[slist[lane]] * -wd : 0.0;
+                        wave_sync();
+                        if (lane < K) xsv[lane] = wd;  // x_S is no longer needed
+                        wave_sync();
+                        for (int i = lane; i < m; i += 64) {
+                            const int f = rowf[i];
+                            if (f & kTight) continue;
+                            const double sg = (f & kRowNeg) ? -1.0 : 1.0;
+                            double ad = (q < n) ? A[int64_t(i) * n + q] : 0.0;
+                            for (int s2 = 0; s2 < K; ++s2) ad = fma(A[int64_t(i) * n + slist[s2]], -xsv[s2], ad);
+                            const double dr = -sg * ad;
+                            const int sen = (f >> 1) & 3;
+                            if ((f & kDeadRow) || sen == kEQ) ok2 &= fabs(dr) <= tol_r;
+                            else if (sen == kLE) ok2 &= dr >= -tol_r;
+                            else if (sen == kGE) ok2 &= -dr >= -tol_r;
+                        }
+                        double g = gain;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+                        const double cq = (q < n) ? c[q] : 0.0;
+                        if (wave_all(ok2) && cq + g > tol_d) cert |= LP_CERT_RAY_OK_BIT;
+                    }
+                }
+            }
+            const bool passed = (st0 == kOptimal) ? (cert & LP_CERT_DUAL_OK_BIT) && (cert & LP_CERT_PRIMAL_OK_BIT)
+                                                  : (cert & LP_CERT_RAY_OK_BIT) != 0;
+            fallback = !passed;
+            if (passed && st0 == kOptimal) {
+                double z = 0.0;
+                for (int j = lane; j < n; j += 64) {
+                    const double xj = (spos[j] >= 0) ? xsv[spos[j]] : 0.0;
+                    x[j] = xj;
+                    z = fma(c[j], xj, z);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
+                if (lane == 0) a.obj[k] = z;
+            } else if (passed) {
+                for (int j = lane; j < n; j += 64) x[j] = __builtin_nan("");
+                if (lane == 0) a.obj[k] = __builtin_inf();
+            }
+        }
+        if (lane == 0) {
+            if (a.stats) a.stats[8 * k + 5] = cert;
+            if (fallback) {
+                const int slot = atomicAdd(a.fb_count, 1);
+                a.fb_ids[slot] = int32_t(k);
+            }
+        }
+        wave_sync();
+        item = lane_get(nxt, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) finish_launch(a.queue, a.done, nullptr);
+}
+
 template <int NT>
 hipError_t launch_t(const CertArgs &a, int grid, hipStream_t s)
 {
@@ -460,9 +850,50 @@ hipError_t launch_certify(int nt, const CertArgs &a, int grid, hipStream_t s)
 
 int certify_blocks_per_cu(int nt, int lds) { return nt == 64 ? occ_t<64>(lds) : occ_t<256>(lds); }
 
+namespace {
+template <int W>
+hipError_t launch_w(const CertArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((certify_wave_kernel<W>), dim3(grid), dim3(64 * W), a.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+template <int W>
+int occ_w(int lds)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)certify_wave_kernel<W>, 64 * W, lds) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+}  // namespace
+
+hipError_t launch_certify_wave(int waves, const CertArgs &a, int grid, hipStream_t s)
+{
+    switch (waves) {
+    case 1: return launch_w<1>(a, grid, s);
+    case 8: return launch_w<8>(a, grid, s);
+    case 16: return launch_w<16>(a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int certify_wave_blocks_per_cu(int waves, int lds)
+{
+    switch (waves) {
+    case 1: return occ_w<1>(lds);
+    case 8: return occ_w<8>(lds);
+    case 16: return occ_w<16>(lds);
+    default: return 0;
+    }
+}
+
 hipError_t certify_configure(int max_lds)
 {
-    const void *fns[] = {(const void *)certify_kernel<64>, (const void *)certify_kernel<256>};
+    const void *fns[] = {(const void *)certify_kernel<64>, (const void *)certify_kernel<256>,
+                         (const void *)certify_wave_kernel<1>, (const void *)certify_wave_kernel<8>,
+                         (const void *)certify_wave_kernel<16>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;

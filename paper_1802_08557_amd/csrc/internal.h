@@ -7,6 +7,8 @@
 
 namespace lpb {
 
+__host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~int64_t(15); }
+
 // Tolerances and limits of one solve (the public lp_options with defaults filled in).
 struct SolveParams {
     double tol_piv;    // a pivot-column entry must exceed this to be eligible (Step 2)
@@ -25,6 +27,11 @@ struct SolveArgs {
     const double *A, *b, *c;  // batch data, layout of include/lpbatch.h
     const int8_t *sense;
     int32_t um, un;           // > 0: every LP is um x un (offsets computed, m/n/offsets unused)
+    int32_t shared;           // 1: A, b, sense hold one LP of m_full x un shared by all LPs
+                              //   (c, x, status, obj and basis_out stay per LP)
+    const int32_t *row_subset;// shared only, optional [num][um]: LP k's row r is row
+    int32_t m_full;           //   row_subset[k*um + r] of the shared LP (um <= m_full);
+                              //   an index outside [0, m_full) makes the LP INVALID_INPUT
     const int32_t *m, *n;     // per-LP sizes when not uniform
     const int64_t *aoff, *roff, *coff;
     int32_t *status;          // outputs
@@ -53,6 +60,9 @@ struct CertArgs {
     const double *A, *b, *c;
     const int8_t *sense;
     int32_t um, un;
+    int32_t shared;           // as in SolveArgs (um = rows of the shared LP)
+    const int32_t *row_subset;// optional: the basis came from a solve on these rows only,
+    int32_t subset_m;         //   subset_m per LP (basis and enter use that LP's numbering)
     const int32_t *m, *n;
     const int64_t *aoff, *roff, *coff;
     int32_t *status;
@@ -67,12 +77,75 @@ struct CertArgs {
     int32_t *queue, *done;
     int32_t lds_bytes;
     double tol_feas, tol_opt; // certificate tolerances (relative, as in SolveParams)
+    // Wavefront kernel only: LDS bytes per wavefront, LU blocks up to kl x kl
+    // kept in LDS (larger ones, up to 64 x 64, in the wavefront's scratch
+    // slot), and whether the shared constraint matrix is copied into LDS.
+    int32_t wave_bytes, kl, stage_a;
 };
+
+// LDS carve-up of one LP in the wavefront certificate kernel (byte offsets).
+struct WaveCertLayout {
+    int64_t rowf, tpos, colf, spos, tlist, slist, order, xs, yv, mat, end;
+};
+
+__host__ __device__ inline WaveCertLayout wave_cert_layout(int m, int n, int kl)
+{
+    WaveCertLayout L;
+    int64_t o = 0;
+    L.rowf = o; o = align16(o + 4 * int64_t(m));
+    L.tpos = o; o = align16(o + 4 * int64_t(m));
+    L.colf = o; o = align16(o + 4 * int64_t(n));
+    L.spos = o; o = align16(o + 4 * int64_t(n));
+    L.tlist = o; o += 256;
+    L.slist = o; o += 256;
+    L.order = o; o += 256;
+    L.xs = o; o += 512;
+    L.yv = o; o += 512;
+    L.mat = o; o = align16(o + 8 * int64_t(kl) * kl);
+    L.end = o;
+    return L;
+}
+
+hipError_t launch_certify_wave(int waves, const CertArgs &a, int grid, hipStream_t s);
+int certify_wave_blocks_per_cu(int waves, int lds_bytes);
 
 hipError_t launch_certify(int nt, const CertArgs &a, int grid, hipStream_t s);
 int certify_blocks_per_cu(int nt, int lds_bytes);
 int64_t certify_lds_bytes(int m, int n, bool with_matrix);
 hipError_t certify_configure(int max_lds);
+
+// Warm-start network (mlp_kernels.hip).  One strided BF16 GEMM with a fused
+// epilogue: C[i][j] = sum_k a[i*sai + k*sak] * b[k*sbk + j*sbj] (+ bias[j]);
+// zeroed where mask[i*ldc + j] <= 0 when mask is set; stored as FP32 (c32)
+// and/or rounded to BF16 (c16, after a ReLU when relu is set).
+struct MlpGemm {
+    int M, N, K;
+    const uint16_t *a, *b;
+    int64_t sai, sak, sbk, sbj;
+    const float *bias, *mask;
+    float *c32;
+    uint16_t *c16;
+    int64_t ldc;
+    int relu;
+};
+
+struct MlpAdam {
+    float lr, wd, beta1, beta2, eps, bc1, bc2;  // bc = 1 - beta^t
+};
+
+hipError_t launch_mlp_gemm(const MlpGemm &g, hipStream_t s);
+hipError_t launch_to_bf16(const float *x, uint16_t *y, int64_t count, hipStream_t s);
+hipError_t launch_bce(const float *S, const uint8_t *Y, int64_t B, int O, float *dS, uint16_t *dS16,
+                      float *row_loss, float *loss, hipStream_t s);
+hipError_t launch_colsum(const float *dZ, int64_t B, int N, float *db, hipStream_t s);
+hipError_t launch_adamw(float *w, const float *g, float *m, float *v, uint16_t *w16, int64_t count,
+                        const MlpAdam &h, const int64_t (&decay)[6], hipStream_t s);
+hipError_t launch_cast_params(const float *w, uint16_t *w16, int64_t count, hipStream_t s);
+hipError_t launch_topk(const float *S, int64_t B, int O, int k, int32_t *out, hipStream_t s);
+
+// Closed-form box LPs (hyperbox_kernels.hip).
+hipError_t launch_hyperbox(int64_t num, int n, const double *lo, const double *hi, const double *l,
+                           int shared_box, double *value, double *x, hipStream_t s);
 
 // Bland index convention shared by every kernel: structural j -> j, the
 // slack/surplus of row i -> n + i, the artificial of row i -> n + m + i.
@@ -100,7 +173,6 @@ hipError_t simplex_wave_configure(int max_lds);
 // Size of the LDS control block + index arrays + pivot row/column buffers for an
 // LP with m rows and at most ncol_max non-basic columns, and the byte offset where
 // an LDS-resident tableau would start.  Host and device compute the same layout.
-__host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~int64_t(15); }
 
 struct LdsLayout {
     int64_t ctrl, basis, nonb, rowf, colrow, pcol, prow, tab, end_aux;

@@ -19,123 +19,18 @@
 
 #include "lpbatch.h"
 #include "internal.h"
+#include "ctx.h"
 
-namespace {
-
+namespace lpb {
 thread_local std::string g_last_error;
-
-int fail(int code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
 }
-
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(LP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
-    } while (0)
-
-// Grow-only device buffer.
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t need)
-    {
-        if (need <= bytes) return LP_OK;
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        size_t want = std::max(need, size_t(4096));
-        if (hipMalloc(&p, want) != hipSuccess) {
-            p = nullptr;
-            return fail(LP_ERR_NOMEM, "hipMalloc of %zu bytes failed", want);
-        }
-        bytes = want;
-        return LP_OK;
-    }
-    void release()
-    {
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-};
-
-struct KernelTime {
-    const char *name;
-    hipEvent_t start, stop;
-};
-
-}  // namespace
-
-struct lp_ctx {
-    int device = 0;
-    bool counters_dirty = false;  // a failed call may have left work counters non-zero
-    int num_cu = 0;
-    int max_lds = 0;
-    DevBuf scratch, meta, counters;
-    std::vector<KernelTime> times;
-    std::vector<hipEvent_t> event_pool;
-    size_t events_used = 0;
-};
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        hipGetDevice(&prev);
-        if (prev != dev) hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        hipGetDevice(&cur);
-        if (prev >= 0 && cur != prev) hipSetDevice(prev);
-    }
-};
-
-hipEvent_t take_event(lp_ctx *ctx)
-{
-    if (ctx->events_used == ctx->event_pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        ctx->event_pool.push_back(e);
-    }
-    return ctx->event_pool[ctx->events_used++];
-}
-
-// Records kernel timing events around a launch when asked to.
-struct Timer {
-    lp_ctx *ctx;
-    bool on;
-    hipStream_t s;
-    KernelTime kt{};
-    Timer(lp_ctx *c, bool enabled, hipStream_t st, const char *name) : ctx(c), on(enabled), s(st)
-    {
-        if (!on) return;
-        kt.name = name;
-        kt.start = take_event(ctx);
-        kt.stop = take_event(ctx);
-        if (!kt.start || !kt.stop) { on = false; return; }
-        hipEventRecord(kt.start, s);
-    }
-    void done()
-    {
-        if (!on) return;
-        hipEventRecord(kt.stop, s);
-        ctx->times.push_back(kt);
-        on = false;
-    }
-};
+using lpb::fail;
+using lpb::DevBuf;
+using lpb::DeviceGuard;
+using lpb::Timer;
 
 lpb::SolveParams fill_params(const lp_options &o, bool fp32)
 {
@@ -175,6 +70,37 @@ bool wave_fit(const lp_ctx *ctx, int64_t mk, int64_t nk, bool fp32)
 // host-built id lists already on the device (wave_ids, and block ids at the
 // front of defer_ids), or -- when list_count is set -- the device list
 // list_ids[0 .. *list_count), all offered to the wavefront kernel first.
+// One persistent launch of the wavefront kernel over ids[0 .. num) (or the
+// device list ids[0 .. *list_count)); LPs it cannot take are appended to
+// defer_ids from defer_base on.
+int launch_wave(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, PassCounters pc, const int32_t *ids, int64_t num,
+                const int32_t *list_count, int wm_max, int wn_max, int32_t *defer_ids, int32_t defer_base,
+                hipStream_t stream, bool timing, const char *name)
+{
+    const int rb = wm_max > 64 ? 2 : 1;
+    lpb::SolveArgs w = a;
+    w.num = num;
+    w.ids = ids;
+    w.num_dev = list_count;
+    w.id_base = 0;
+    w.queue = pc.wq;
+    w.done = pc.wd;
+    w.reset_extra = const_cast<int32_t *>(list_count);  // nothing reads it after this launch
+    w.defer_ids = defer_ids;
+    w.defer_count = pc.defer;
+    w.defer_base = defer_base;
+    // Budget for the common case of no surplus columns; an LP needing more is deferred.
+    const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) + lpb::wave_tab_bytes(wm_max, wn_max + 1, fp32);
+    w.lds_bytes = int32_t(lds);
+    const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
+    if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
+    const int64_t grid = std::min<int64_t>(num, int64_t(per_cu) * ctx->num_cu);
+    Timer t(ctx, timing, stream, name);
+    HIP_TRY(lpb::launch_simplex_wave(fp32, rb, w, int(grid), stream));
+    t.done();
+    return LP_OK;
+}
+
 int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &opts, PassCounters pc,
                const int32_t *wave_ids, int64_t n_wave, int wm_max, int wn_max, int64_t n_block,
                int32_t *defer_ids, const int32_t *list_ids, const int32_t *list_count,
@@ -183,27 +109,9 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
     const bool fp32 = P.fp32;
     const int64_t ts = P.ts;
     if (n_wave > 0) {
-        const int rb = wm_max > 64 ? 2 : 1;
-        lpb::SolveArgs w = a;
-        w.num = list_count ? P.num : n_wave;
-        w.ids = list_count ? list_ids : wave_ids;
-        w.num_dev = list_count;
-        w.id_base = 0;
-        w.queue = pc.wq;
-        w.done = pc.wd;
-        w.reset_extra = const_cast<int32_t *>(list_count);  // nothing reads it after this launch
-        w.defer_ids = defer_ids;
-        w.defer_count = pc.defer;
-        w.defer_base = int32_t(n_block);
-        // Budget for the common case of no surplus columns; an LP needing more is deferred.
-        const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) + lpb::wave_tab_bytes(wm_max, wn_max + 1, fp32);
-        w.lds_bytes = int32_t(lds);
-        const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
-        if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
-        const int64_t grid = std::min<int64_t>(w.num, int64_t(per_cu) * ctx->num_cu);
-        Timer t(ctx, timing, stream, wname);
-        HIP_TRY(lpb::launch_simplex_wave(fp32, rb, w, int(grid), stream));
-        t.done();
+        int rc = launch_wave(ctx, fp32, a, pc, list_count ? list_ids : wave_ids, list_count ? P.num : n_wave,
+                             list_count, wm_max, wn_max, defer_ids, int32_t(n_block), stream, timing, wname);
+        if (rc != LP_OK) return rc;
     }
     // Workgroup kernel: the LPs given to it plus the ones the wavefront deferred.
     const int ncol_worst = P.n_max + P.m_max;
@@ -259,11 +167,168 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
     return LP_OK;
 }
 
+
+// ---- Size bins for uneven batches ------------------------------------------
+// LPs the wavefront kernel cannot take are grouped by the cell count of their
+// tableau; each bin gets its own persistent launch of the workgroup kernel
+// with its own workgroup size and placement, from the context's tuning table
+// (filled by the autotuner) or a size heuristic.  Inside a bin the work queue
+// hands out the most expensive LPs first, so the launch ends on small ones.
+constexpr int kBins = 4;
+
+int bin_of(int64_t m, int64_t n)
+{
+    const int64_t cells = (m + 1) * (n + 1);
+    return cells <= 64 * 64 ? 0 : cells <= 128 * 128 ? 1 : cells <= 256 * 256 ? 2 : 3;
+}
+
+int default_threads(int bin) { return bin == 0 ? 64 : bin == 1 ? 128 : bin == 2 ? 256 : 512; }
+
+// Estimated work of one LP: pivots grow with m + n, each pivot touches m x n cells.
+double lp_cost(int64_t m, int64_t n) { return double(m) * double(n) * double(m + n); }
+
+struct BinLaunch {
+    int m_max = 0, n_max = 0;
+    int nt = 64;
+    bool force_hbm = false;
+};
+
+// One persistent launch of the workgroup kernel over the work items
+// 0 .. num - 1 (host-known count) or 0 .. id_base + *num_dev - 1 (device-side
+// count); item t is LP ids[t] (LP t when ids is NULL).
+int launch_block(lp_ctx *ctx, bool fp32, lpb::SolveArgs a, const BinLaunch &B, const int32_t *ids, int64_t num,
+                 const int32_t *num_dev, int32_t id_base, int32_t *reset_extra, int64_t grid_cap, int32_t *q,
+                 int32_t *d, hipStream_t stream, bool timing, const char *name)
+{
+    const int64_t ts = fp32 ? 4 : 8;
+    const int ncol_worst = B.n_max + B.m_max;
+    lpb::LdsLayout L = lpb::lds_layout(B.m_max, ncol_worst, ts, lpb::simplex_ctrl_bytes(fp32));
+    const int64_t tab_common = int64_t(B.m_max + 1) * lpb::tableau_ld(B.n_max + 1) * ts;
+    const int64_t tab_worst = int64_t(B.m_max + 1) * lpb::tableau_ld(ncol_worst + 1) * ts;
+    int64_t lds = L.tab;
+    const bool want_lds = !B.force_hbm && L.tab + tab_common <= ctx->max_lds;
+    if (want_lds) lds = L.tab + tab_common;
+    if (lds > ctx->max_lds)
+        return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index arrays "
+                    "(device limit %d)", B.m_max, ncol_worst, (long long)lds, ctx->max_lds);
+    a.lds_bytes = int32_t(lds);
+    a.force_hbm = B.force_hbm;
+    const int per_cu = lpb::simplex_blocks_per_cu(fp32, B.nt, int(lds));
+    if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for %d threads, %lld B LDS", B.nt, (long long)lds);
+    int64_t grid = std::min<int64_t>(num, int64_t(per_cu) * ctx->num_cu);
+    if (grid_cap > 0) grid = std::min(grid, grid_cap);
+    if (grid < 1) return LP_OK;
+    if (!want_lds || tab_worst > tab_common) {
+        a.slot_bytes = lpb::align16(tab_worst);
+        int rc = ctx->scratch.ensure(size_t(a.slot_bytes) * size_t(grid));
+        if (rc != LP_OK) return rc;
+        a.scratch = static_cast<char *>(ctx->scratch.p);
+    }
+    a.queue = q;
+    a.done = d;
+    a.ids = ids;
+    a.num = num;
+    a.num_dev = num_dev;
+    a.id_base = id_base;
+    a.reset_extra = reset_extra;
+    Timer t(ctx, timing, stream, name);
+    HIP_TRY(lpb::launch_simplex(fp32, B.nt, a, int(grid), stream));
+    t.done();
+    return LP_OK;
+}
+
+// Trial launches of one bin's sample: every (workgroup size, placement)
+// candidate is timed with events on `stream` and the fastest stored in the
+// context's table.  Synchronous.  The sampled LPs' outputs are overwritten
+// by the real solve that follows.
+int autotune_bin(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, BinLaunch B, int bin, const int32_t *d_sample,
+                 int64_t n_sample, int32_t *q, int32_t *d, hipStream_t stream)
+{
+    hipEvent_t e0 = lpb::take_event(ctx), e1 = lpb::take_event(ctx);
+    if (!e0 || !e1) return fail(LP_ERR_HIP, "could not create timing events");
+    float best = 1e30f;
+    lpb::TuneEntry choice{default_threads(bin), 0};
+    const int cand_nt[4] = {64, 128, 256, 512};
+    for (int hbm = 0; hbm < 2; ++hbm)
+        for (int nt : cand_nt) {
+            BinLaunch T = B;
+            T.nt = nt;
+            T.force_hbm = hbm != 0;
+            HIP_TRY(hipEventRecord(e0, stream));
+            int rc = launch_block(ctx, fp32, a, T, d_sample, n_sample, nullptr, 0, nullptr, 0, q, d, stream, false, "");
+            if (rc != LP_OK) return rc;
+            HIP_TRY(hipEventRecord(e1, stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; choice = lpb::TuneEntry{nt, hbm}; }
+        }
+    ctx->tune[lpb::tune_key(bin, fp32)] = choice;
+    ctx->events_used -= 2;  // give the two events back to the pool
+    return LP_OK;
+}
+
+
+struct BinSpan {
+    int bin;
+    int64_t offset, count;  // in the host-built id list
+    int m_max, n_max;
+    int64_t sample_offset, sample_count;
+};
+
+// Main pass of an uneven batch: the wavefront kernel for the LPs it fits,
+// one workgroup-kernel launch per size bin (largest bin first), then one
+// small launch for the LPs the wavefront kernel deferred.
+int queue_binned(lp_ctx *ctx, const Plan &P, const lpb::SolveArgs &a, const lp_options &opts, PassCounters pc,
+                 const int32_t *wave_ids, int64_t n_wave, int wm_max, int wn_max, int32_t *d_block,
+                 int64_t n_block, const std::vector<BinSpan> &bins, const int32_t *d_samples, bool autotune,
+                 hipStream_t stream, bool timing, const char *wname, const char *bname)
+{
+    const bool fp32 = P.fp32;
+    for (const BinSpan &sp : bins) {
+        if (!autotune || sp.sample_count < 1 || ctx->tune.count(lpb::tune_key(sp.bin, fp32))) continue;
+        BinLaunch B;
+        B.m_max = sp.m_max;
+        B.n_max = sp.n_max;
+        int rc = autotune_bin(ctx, fp32, a, B, sp.bin, d_samples + sp.sample_offset, sp.sample_count, pc.bq, pc.bd,
+                              stream);
+        if (rc != LP_OK) return rc;
+    }
+    if (n_wave > 0) {
+        int rc = launch_wave(ctx, fp32, a, pc, wave_ids, n_wave, nullptr, wm_max, wn_max, d_block, int32_t(n_block),
+                             stream, timing, wname);
+        if (rc != LP_OK) return rc;
+    }
+    for (const BinSpan &sp : bins) {
+        BinLaunch B;
+        B.m_max = sp.m_max;
+        B.n_max = sp.n_max;
+        auto it = ctx->tune.find(lpb::tune_key(sp.bin, fp32));
+        B.nt = it != ctx->tune.end() ? it->second.nt : default_threads(sp.bin);
+        B.force_hbm = it != ctx->tune.end() ? it->second.force_hbm != 0 : false;
+        if (opts.placement == LP_PLACE_HBM) B.force_hbm = true;
+        int rc = launch_block(ctx, fp32, a, B, d_block + sp.offset, sp.count, nullptr, 0, nullptr, 0, pc.bq, pc.bd,
+                              stream, timing, bname);
+        if (rc != LP_OK) return rc;
+    }
+    if (n_wave > 0) {
+        // The deferred LPs (few, with at most 128 rows): one workgroup per CU.
+        BinLaunch B;
+        B.m_max = wm_max;
+        B.n_max = wn_max;
+        B.nt = 64;
+        int rc = launch_block(ctx, fp32, a, B, d_block + n_block, n_wave, pc.defer, 0, pc.defer, ctx->num_cu,
+                              pc.bq, pc.bd, stream, timing, bname);
+        if (rc != LP_OK) return rc;
+    }
+    return LP_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *lp_last_error(void) { return g_last_error.c_str(); }
+const char *lp_last_error(void) { return lpb::g_last_error.c_str(); }
 
 void lp_options_init(lp_options *o)
 {
@@ -316,6 +381,9 @@ void lp_ctx_destroy(lp_ctx *ctx)
     ctx->scratch.release();
     ctx->meta.release();
     ctx->counters.release();
+    lpb::MlpState &M = ctx->mlp;
+    for (lpb::DevBuf *d : {&M.params, &M.params16, &M.adam_m, &M.adam_v, &M.grads, &M.act, &M.misc})
+        d->release();
     for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
     delete ctx;
 }
@@ -361,6 +429,17 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     }
     P.fp32 = opts.precision == LP_PREC_FP32_CERT64;
     P.ts = P.fp32 ? 4 : 8;
+    // Shared constraints, optionally screened: the first pass solves every LP
+    // on its subset_m rows only, and the certificate judges the basis on all rows.
+    const bool shared = opts.shared != 0;
+    const bool screened = opts.row_subset != nullptr;
+    if (screened && !shared) return fail(LP_ERR_ARG, "row_subset needs shared = 1");
+    if (shared && !P.uniform) return fail(LP_ERR_ARG, "shared = 1 needs every m[k] and every n[k] equal");
+    if (screened && (opts.subset_m < 1 || opts.subset_m > P.m0))
+        return fail(LP_ERR_ARG, "subset_m = %d must lie in 1..%d", opts.subset_m, P.m0);
+    const Plan P_full = P;
+    if (screened) P.m0 = P.m_max = opts.subset_m;
+    const bool certify = P.fp32 || screened;
     hipStream_t stream = reinterpret_cast<hipStream_t>(opts.stream);
     DeviceGuard g(ctx->device);
 
@@ -371,15 +450,23 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     std::vector<int32_t> wave_ids, block_ids;
     int64_t n_wave = 0, rows = 0;
     int wm_max = 0, wn_max = 0;
-    for (int64_t k = 0; k < num_lps; ++k) {
-        const bool w = auto_kernel && wave_fit(ctx, m[k], n[k], P.fp32);
-        if (w) {
-            ++n_wave;
-            wm_max = std::max(wm_max, m[k]);
-            wn_max = std::max(wn_max, n[k]);
+    if (P.uniform) {
+        const bool w = auto_kernel && wave_fit(ctx, P.m0, P.n0, P.fp32);
+        n_wave = w ? num_lps : 0;
+        wm_max = w ? P.m0 : 0;
+        wn_max = w ? P.n0 : 0;
+        rows = num_lps * int64_t(P.m0);
+    } else {
+        for (int64_t k = 0; k < num_lps; ++k) {
+            const bool w = auto_kernel && wave_fit(ctx, m[k], n[k], P.fp32);
+            if (w) {
+                ++n_wave;
+                wm_max = std::max(wm_max, m[k]);
+                wn_max = std::max(wn_max, n[k]);
+            }
+            rows += m[k];
+            (w ? wave_ids : block_ids).push_back(int32_t(k));
         }
-        rows += m[k];
-        if (!P.uniform) (w ? wave_ids : block_ids).push_back(int32_t(k));
     }
     const int64_t n_block = num_lps - n_wave;
 
@@ -389,6 +476,9 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     a.status = status; a.x = x; a.obj = obj;
     a.stats = opts.stats;
     a.prm = fill_params(opts, P.fp32);
+    a.shared = shared ? 1 : 0;
+    a.row_subset = opts.row_subset;
+    a.m_full = P_full.m0;
 
     // Device metadata: [m][n][aoff][roff][coff] (non-uniform only); id lists
     // (capacity num_lps each): wavefront ids, deferred/workgroup ids, fallback
@@ -396,7 +486,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     // entering variables [num_lps].
     const size_t sz_shape = P.uniform ? 0 : size_t(num_lps) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
     const size_t sz_ids = size_t(num_lps) * sizeof(int32_t);
-    const size_t sz_fp32 = P.fp32 ? lpb::align16(size_t(rows) * 4) + lpb::align16(sz_ids) : 0;
+    const size_t sz_fp32 = certify ? lpb::align16(size_t(rows) * 4) + lpb::align16(sz_ids) : 0;
     {
         int rc = ctx->meta.ensure(sz_shape + 4 * lpb::align16(sz_ids) + sz_fp32);
         if (rc != LP_OK) return rc;
@@ -408,11 +498,67 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     int32_t *d_fb_defer = reinterpret_cast<int32_t *>(meta + sz_shape + 3 * lpb::align16(sz_ids));
     int32_t *d_basis = reinterpret_cast<int32_t *>(meta + sz_shape + 4 * lpb::align16(sz_ids));
     int32_t *d_enter = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(d_basis) + lpb::align16(size_t(rows) * 4));
+    // Uneven batches with automatic kernel choice: size bins for the LPs the
+    // wavefront kernel cannot take, each bin ordered by estimated work
+    // (largest first), bins largest first; plus a sample of every bin for the
+    // autotuner.
+    // A uniform batch the workgroup kernel takes is a single bin, binned when
+    // it is tuned or to be tuned.
+    const bool autotune = (opts.flags & LP_FLAG_AUTOTUNE) != 0;
+    const bool binned = auto_kernel && n_block > 0 &&
+                        (!P.uniform || autotune || ctx->tune.count(lpb::tune_key(bin_of(P.m0, P.n0), P.fp32)));
+    std::vector<BinSpan> bins;
+    std::vector<int32_t> samples;
+    if (binned && P.uniform) {
+        BinSpan sp;
+        sp.bin = bin_of(P.m0, P.n0);
+        sp.offset = 0;
+        sp.count = num_lps;
+        sp.m_max = P.m0;
+        sp.n_max = P.n0;
+        sp.sample_offset = 0;
+        sp.sample_count = std::min<int64_t>(num_lps, 256);
+        for (int64_t t = 0; t < sp.sample_count; ++t) samples.push_back(int32_t(t * num_lps / sp.sample_count));
+        bins.push_back(sp);
+    } else if (binned) {
+        std::vector<int32_t> by_bin[kBins];
+        for (int32_t k : block_ids) by_bin[bin_of(m[k], n[k])].push_back(k);
+        block_ids.clear();
+        for (int bi = kBins - 1; bi >= 0; --bi) {
+            std::vector<int32_t> &v = by_bin[bi];
+            if (v.empty()) continue;
+            std::stable_sort(v.begin(), v.end(),
+                             [&](int32_t x, int32_t y) { return lp_cost(m[x], n[x]) > lp_cost(m[y], n[y]); });
+            BinSpan sp;
+            sp.bin = bi;
+            sp.offset = int64_t(block_ids.size());
+            sp.count = int64_t(v.size());
+            sp.m_max = 0;
+            sp.n_max = 0;
+            for (int32_t k : v) { sp.m_max = std::max(sp.m_max, m[k]); sp.n_max = std::max(sp.n_max, n[k]); }
+            // Every stride-th LP of the cost-ordered bin, at most 256.
+            sp.sample_offset = int64_t(samples.size());
+            const int64_t want = std::min<int64_t>(sp.count, 256);
+            for (int64_t t = 0; t < want; ++t) samples.push_back(v[size_t(t * sp.count / want)]);
+            sp.sample_count = want;
+            block_ids.insert(block_ids.end(), v.begin(), v.end());
+            bins.push_back(sp);
+        }
+    }
     if (P.uniform) {
         a.um = P.m0;
         a.un = P.n0;
+        if (autotune && !samples.empty()) {
+            HIP_TRY(hipMemcpyAsync(d_fb_defer, samples.data(), samples.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
     } else {
-        std::vector<char> host(sz_shape + lpb::align16(sz_ids) + size_t(n_block) * sizeof(int32_t));
+        const size_t sample_at = sz_shape + 3 * lpb::align16(sz_ids);
+        std::vector<char> host(samples.empty() ? sz_shape + lpb::align16(sz_ids) + size_t(n_block) * sizeof(int32_t)
+                                                : sample_at + samples.size() * sizeof(int32_t));
+        if (!samples.empty())
+            std::copy(samples.begin(), samples.end(), reinterpret_cast<int32_t *>(host.data() + sample_at));
         int32_t *hm = reinterpret_cast<int32_t *>(host.data());
         int32_t *hn = hm + num_lps;
         int64_t *ha = reinterpret_cast<int64_t *>(hn + num_lps);
@@ -447,23 +593,31 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     }
     ctx->counters_dirty = true;  // until every launch below has been queued
 
-    if (P.fp32) {
+    if (certify) {
         a.basis_out = d_basis;
         a.enter_out = d_enter;
     }
-    int rc = queue_pass(ctx, P, a, opts, main_pc, P.uniform ? nullptr : d_wave_ids, n_wave, wm_max, wn_max,
-                        n_block, d_defer_ids,
-                        nullptr, nullptr, stream, timing, P.fp32 ? "simplex_wave_fp32" : "simplex_wave_fp64",
-                        P.fp32 ? "simplex_block_fp32" : "simplex_block_fp64");
+    const char *wname = screened ? (P.fp32 ? "simplex_wave_fp32_screened" : "simplex_wave_fp64_screened")
+                                 : (P.fp32 ? "simplex_wave_fp32" : "simplex_wave_fp64");
+    const char *bname = screened ? (P.fp32 ? "simplex_block_fp32_screened" : "simplex_block_fp64_screened")
+                                 : (P.fp32 ? "simplex_block_fp32" : "simplex_block_fp64");
+    int rc = binned ? queue_binned(ctx, P, a, opts, main_pc, d_wave_ids, n_wave, wm_max, wn_max,
+                                   P.uniform ? nullptr : d_defer_ids, n_block, bins, d_fb_defer, autotune, stream,
+                                   timing, wname, bname)
+                    : queue_pass(ctx, P, a, opts, main_pc, P.uniform ? nullptr : d_wave_ids, n_wave, wm_max,
+                                 wn_max, n_block, d_defer_ids, nullptr, nullptr, stream, timing, wname, bname);
     if (rc != LP_OK) return rc;
 
-    if (P.fp32) {
+    if (certify) {
         // FP64 certificate of every final basis, then an FP64 re-solve of the rest.
         lpb::CertArgs ca;
         std::memset(&ca, 0, sizeof ca);
         ca.num = num_lps;
         ca.A = A; ca.b = b; ca.c = c; ca.sense = sense;
-        ca.um = a.um; ca.un = a.un; ca.m = a.m; ca.n = a.n;
+        ca.um = P_full.uniform ? P_full.m0 : 0; ca.un = a.un; ca.m = a.m; ca.n = a.n;
+        ca.shared = a.shared;
+        ca.row_subset = opts.row_subset;
+        ca.subset_m = screened ? opts.subset_m : 0;
         ca.aoff = a.aoff; ca.roff = a.roff; ca.coff = a.coff;
         ca.status = status; ca.x = x; ca.obj = obj; ca.stats = opts.stats;
         ca.basis = d_basis; ca.enter = d_enter;
@@ -472,31 +626,67 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         const lpb::SolveParams p64 = fill_params(opts, false);
         ca.tol_feas = p64.tol_feas;
         ca.tol_opt = p64.tol_opt;
-        // One wavefront per LP; LU blocks up to 32 x 32 in LDS, larger ones in the
-        // workgroup's device-memory slot (decided per LP by the kernel).
-        const int kmax = std::min(P.m_max, P.n_max);
-        const int cnt_nt = 64;
-        const int64_t kl = std::min(kmax, 32);
-        const int64_t clds = lpb::certify_lds_bytes(P.m_max, P.n_max, false) + 8 * kl * kl;
-        if (clds > ctx->max_lds) return fail(LP_ERR_ARG, "LP too large for the certificate kernel");
-        ca.lds_bytes = int32_t(clds);
-        const int per_cu = lpb::certify_blocks_per_cu(cnt_nt, int(clds));
-        if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
-        const int64_t cgrid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
-        ca.slot_bytes = lpb::align16(8 * int64_t(kmax) * kmax);
-        {
-            // The LU slots share the tableau scratch (the FP32 pass has finished with it
-            // by the time the certificate kernel runs on the same stream).
+        const int kmax = std::min(P_full.m_max, P_full.n_max);
+        if (kmax <= 64) {
+            // One wavefront per LP (at most 64 basic structurals); LU blocks up to
+            // kl x kl in LDS, larger ones in the wavefront's device-memory slot.
+            // Shared constraints are copied into LDS once per workgroup of W
+            // wavefronts when they fit next to W wavefront regions.
+            const int64_t a_bytes = lpb::align16(8 * int64_t(P_full.m0) * P_full.n0);
+            int W = 1, kl = std::min(kmax, 32), stage = 0;
+            int64_t wb = lpb::wave_cert_layout(P_full.m_max, P_full.n_max, kl).end, lds = wb;
+            if (shared && a_bytes <= 65536) {
+                const int cand_w[4] = {16, 16, 8, 8};
+                const int cand_k[4] = {32, 24, 32, 24};
+                for (int q = 0; q < 4 && !stage; ++q) {
+                    const int klq = std::min(kmax, cand_k[q]);
+                    const int64_t wbq = lpb::wave_cert_layout(P_full.m_max, P_full.n_max, klq).end;
+                    if (a_bytes + cand_w[q] * wbq <= ctx->max_lds) {
+                        W = cand_w[q]; kl = klq; wb = wbq; lds = a_bytes + W * wbq; stage = 1;
+                    }
+                }
+            }
+            if (lds > ctx->max_lds) return fail(LP_ERR_ARG, "LP too large for the certificate kernel");
+            ca.wave_bytes = int32_t(wb);
+            ca.kl = kl;
+            ca.stage_a = stage;
+            ca.lds_bytes = int32_t(lds);
+            const int per_cu = lpb::certify_wave_blocks_per_cu(W, int(lds));
+            if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
+            const int64_t cgrid = std::min<int64_t>((num_lps + W - 1) / W, int64_t(per_cu) * ctx->num_cu);
+            if (kmax > kl) {
+                ca.slot_bytes = 8 * 64 * 64;
+                // The LU slots share the tableau scratch (the first pass has finished
+                // with it by the time the certificate kernel runs on the same stream).
+                int rc2 = ctx->scratch.ensure(
+                    std::max<size_t>(ctx->scratch.bytes, size_t(ca.slot_bytes) * size_t(cgrid) * W));
+                if (rc2 != LP_OK) return rc2;
+                ca.scratch = static_cast<char *>(ctx->scratch.p);
+            }
+            Timer t(ctx, timing, stream, "certify_fp64");
+            HIP_TRY(lpb::launch_certify_wave(W, ca, int(cgrid), stream));
+            t.done();
+        } else {
+            // One workgroup of 64 threads per LP; LU blocks up to 32 x 32 in LDS,
+            // larger ones in the workgroup's device-memory slot.
+            const int cnt_nt = 64;
+            const int64_t kl = std::min(kmax, 32);
+            const int64_t clds = lpb::certify_lds_bytes(P_full.m_max, P_full.n_max, false) + 8 * kl * kl;
+            if (clds > ctx->max_lds) return fail(LP_ERR_ARG, "LP too large for the certificate kernel");
+            ca.lds_bytes = int32_t(clds);
+            const int per_cu = lpb::certify_blocks_per_cu(cnt_nt, int(clds));
+            if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
+            const int64_t cgrid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
+            ca.slot_bytes = lpb::align16(8 * int64_t(kmax) * kmax);
             int rc2 = ctx->scratch.ensure(std::max<size_t>(ctx->scratch.bytes, size_t(ca.slot_bytes) * size_t(cgrid)));
             if (rc2 != LP_OK) return rc2;
             ca.scratch = static_cast<char *>(ctx->scratch.p);
-        }
-        {
             Timer t(ctx, timing, stream, "certify_fp64");
             HIP_TRY(lpb::launch_certify(cnt_nt, ca, int(cgrid), stream));
             t.done();
         }
-        Plan P64 = P;
+        // FP64 re-solve of every LP the certificate rejected, on all of its rows.
+        Plan P64 = P_full;
         P64.fp32 = false;
         P64.ts = 8;
         lpb::SolveArgs a64 = a;
@@ -504,14 +694,24 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         a64.basis_out = nullptr;
         a64.enter_out = nullptr;
         a64.refine_stats = 1;
+        a64.row_subset = nullptr;
+        if (P_full.uniform) a64.um = P_full.m0;
         int64_t n_wave64 = 0;
         int wm64 = 0, wn64 = 0;
-        for (int64_t k = 0; k < num_lps && auto_kernel; ++k)
-            if (wave_fit(ctx, m[k], n[k], false)) {
-                ++n_wave64;
-                wm64 = std::max(wm64, m[k]);
-                wn64 = std::max(wn64, n[k]);
+        if (P_full.uniform) {
+            if (auto_kernel && wave_fit(ctx, P_full.m0, P_full.n0, false)) {
+                n_wave64 = num_lps;
+                wm64 = P_full.m0;
+                wn64 = P_full.n0;
             }
+        } else {
+            for (int64_t k = 0; k < num_lps && auto_kernel; ++k)
+                if (wave_fit(ctx, m[k], n[k], false)) {
+                    ++n_wave64;
+                    wm64 = std::max(wm64, m[k]);
+                    wn64 = std::max(wn64, n[k]);
+                }
+        }
         rc = queue_pass(ctx, P64, a64, opts, fb_pc, nullptr, n_wave64 > 0 ? 1 : 0, wm64, wn64, 0, d_fb_defer,
                         d_fb_ids, fb_count, stream, timing, "simplex_wave_fp64_resolve",
                         "simplex_block_fp64_resolve");
@@ -520,6 +720,37 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     ctx->counters_dirty = false;
     if (opts.flags & LP_FLAG_SYNC) HIP_TRY(hipStreamSynchronize(stream));
     return LP_OK;
+}
+
+int lp_hyperbox_support(lp_ctx *ctx, int64_t num, int32_t n, const double *lo, const double *hi,
+                        const double *l, int32_t shared_box, double *value, double *x, void *stream)
+{
+    if (!ctx) return fail(LP_ERR_ARG, "ctx is NULL");
+    if (num < 0) return fail(LP_ERR_ARG, "num is negative (%lld)", (long long)num);
+    if (n < 1 || n > 1000000) return fail(LP_ERR_ARG, "n = %d must lie in 1..1000000", n);
+    if (num == 0) return LP_OK;
+    if (!lo || !hi || !l || !value) return fail(LP_ERR_ARG, "a box pointer is NULL");
+    if (num > (int64_t(1) << 40) / n) return fail(LP_ERR_ARG, "batch size overflows");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(lpb::launch_hyperbox(num, n, lo, hi, l, shared_box ? 1 : 0, value, x,
+                                 static_cast<hipStream_t>(stream)));
+    return LP_OK;
+}
+
+int lp_ctx_tuning(lp_ctx *ctx, int32_t *entries, int cap)
+{
+    if (!ctx) return fail(LP_ERR_ARG, "lp_ctx_tuning: ctx is NULL");
+    int i = 0;
+    for (const auto &kv : ctx->tune) {
+        if (entries && i < cap) {
+            entries[4 * i + 0] = kv.first / 2;
+            entries[4 * i + 1] = kv.first % 2;
+            entries[4 * i + 2] = kv.second.nt;
+            entries[4 * i + 3] = kv.second.force_hbm;
+        }
+        ++i;
+    }
+    return i;
 }
 
 int lp_ctx_kernel_times(lp_ctx *ctx, const char **names, float *ms, int cap)

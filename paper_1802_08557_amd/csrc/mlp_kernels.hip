@@ -1,0 +1,266 @@
+// mlp_kernels.hip -- the warm-start scoring network (20 -> 256 -> 256 -> 120,
+// ReLU) on the matrix cores: BF16 operands, FP32 accumulation.
+//
+// Every layer, forward and backward, is one launch of a strided GEMM
+//     C[i][j] = sum_k A(i, k) B(k, j),  A(i, k) = a[i*sai + k*sak],
+//                                        B(k, j) = b[k*sbk + j*sbj]
+// on v_mfma_f32_16x16x16_bf16 tiles, one wavefront per 32 x 32 block of C,
+// followed by a fused epilogue (bias, ReLU mask of the forward activation,
+// FP32 and/or rounded BF16 stores).  The products are small (the widest is
+// 256 x 256), so one strided kernel serves the six backward shapes too; the
+// forward reads both operands along k with 8-byte loads.
+//
+// The remaining kernels are elementwise or row-wise: FP32 -> BF16 input
+// conversion, the logistic loss and its gradient, bias gradients (column sums
+// in a fixed order), AdamW on the FP32 master weights with a fresh BF16 copy,
+// and the per-direction top-k of the scores.  Every reduction runs in a fixed
+// order, so a training step is deterministic.
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace lpb {
+namespace {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> bfloat16 bits, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// Four consecutive-k operand values of row (or column) r, k = k0 .. k0 + 3;
+// zero outside [0, R) x [0, K).
+__device__ __forceinline__ s16x4 load_frag(const uint16_t *p, int r, int R, int64_t sr, int k0, int K,
+                                           int64_t sk)
+{
+    s16x4 v = {0, 0, 0, 0};
+    if (r >= R) return v;
+    const uint16_t *q = p + int64_t(r) * sr;
+    if (sk == 1 && k0 + 3 < K && ((int64_t(r) * sr + k0) & 3) == 0) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(q + k0);
+        v[0] = short(w.x & 0xFFFF);
+        v[1] = short(w.x >> 16);
+        v[2] = short(w.y & 0xFFFF);
+        v[3] = short(w.y >> 16);
+        return v;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (k0 + t < K) v[t] = short(q[int64_t(k0 + t) * sk]);
+    return v;
+}
+
+__global__ __launch_bounds__(64) void gemm_bf16_kernel(MlpGemm g)
+{
+    const int lane = threadIdx.x;
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+        // A fragment: row i0 + 16 a + (lane % 16), k = k0 + 4 (lane / 16) + t;
+        // B fragment: column j0 + 16 b + (lane % 16), same k.
+        s16x4 fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) fa[a] = load_frag(g.a, i0 + 16 * a + r16, g.M, g.sai, k0 + kq, g.K, g.sak);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) fb[b] = load_frag(g.b, j0 + 16 * b + r16, g.N, g.sbj, k0 + kq, g.K, g.sbk);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    // D layout: lane holds column (lane % 16), rows 4 (lane / 16) + t.
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + 16 * b + r16;
+            if (j >= g.N) continue;
+            const float bj = g.bias ? g.bias[j] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i0 + 16 * a + kq + t;
+                if (i >= g.M) continue;
+                float v = acc[a][b][t] + bj;
+                const int64_t o = int64_t(i) * g.ldc + j;
+                if (g.mask && !(g.mask[o] > 0.f)) v = 0.f;
+                if (g.c32) g.c32[o] = v;
+                if (g.c16) g.c16[o] = to_bf16(g.relu ? fmaxf(v, 0.f) : v);
+            }
+        }
+}
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t count)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) y[i] = to_bf16(x[i]);
+}
+
+// dS = (sigmoid(S) - Y) / (B * O) in FP32 and BF16; row_loss[b] = sum over the
+// row of softplus(S) - Y S (summed in column order).
+__global__ void bce_kernel(const float *S, const uint8_t *Y, int64_t B, int O, float *dS, uint16_t *dS16,
+                           float *row_loss)
+{
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const float inv = 1.0f / (float(B) * float(O));
+    float acc = 0.f;
+    for (int j = 0; j < O; ++j) {
+        const int64_t o = b * O + j;
+        const float s = S[o];
+        const float y = Y[o] ? 1.f : 0.f;
+        const float sp = fmaxf(s, 0.f) + log1pf(expf(-fabsf(s)));
+        acc += sp - y * s;
+        const float sg = 1.f / (1.f + expf(-s));
+        const float d = (sg - y) * inv;
+        dS[o] = d;
+        dS16[o] = to_bf16(d);
+    }
+    row_loss[b] = acc;
+}
+
+// Mean of the row losses, one workgroup, fixed order: each thread sums a
+// strided slice, then a tree over the threads.
+__global__ __launch_bounds__(256) void mean_kernel(const float *row_loss, int64_t B, int O, float *out)
+{
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < B; b += 256) s += double(row_loss[b]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = float(part[0] / (double(B) * O));
+}
+
+// db[j] = sum_b dZ[b][j], rows in order.
+__global__ void colsum_kernel(const float *dZ, int64_t B, int N, float *db)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int64_t b = 0; b < B; ++b) s += dZ[b * N + j];
+    db[j] = s;
+}
+
+// AdamW on the FP32 master copy; decay[i] = 1 for weights, 0 for biases.
+__global__ void adamw_kernel(float *w, const float *g, float *m, float *v, uint16_t *w16, int64_t count,
+                             MlpAdam h, int64_t decay_lo0, int64_t decay_hi0, int64_t decay_lo1,
+                             int64_t decay_hi1, int64_t decay_lo2, int64_t decay_hi2)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const bool decay = (i >= decay_lo0 && i < decay_hi0) || (i >= decay_lo1 && i < decay_hi1) ||
+                       (i >= decay_lo2 && i < decay_hi2);
+    const float gi = g[i];
+    const float mi = h.beta1 * m[i] + (1.f - h.beta1) * gi;
+    const float vi = h.beta2 * v[i] + (1.f - h.beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mhat = mi / h.bc1;
+    const float vhat = vi / h.bc2;
+    float wi = w[i];
+    wi = wi - h.lr * mhat / (sqrtf(vhat) + h.eps) - (decay ? h.lr * h.wd * w[i] : 0.f);
+    w[i] = wi;
+    w16[i] = to_bf16(wi);
+}
+
+__global__ void cast_params_kernel(const float *w, uint16_t *w16, int64_t count)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) w16[i] = to_bf16(w[i]);
+}
+
+// Top-k of each row of S [B][O] (O <= 128): one wavefront per row; the entry
+// of rank r (number of entries that are larger, or equal with a lower index)
+// goes to out[b][r] when r < k.
+__global__ __launch_bounds__(64) void topk_kernel(const float *S, int64_t B, int O, int k, int32_t *out)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= B) return;
+    __shared__ float s[128];
+    const int lane = threadIdx.x;
+    for (int j = lane; j < O; j += 64) s[j] = S[b * O + j];
+    __syncthreads();
+    for (int j = lane; j < O; j += 64) {
+        const float v = s[j];
+        int r = 0;
+        for (int t = 0; t < O; ++t) {
+            const float u = s[t];
+            r += (u > v || (u == v && t < j)) ? 1 : 0;
+        }
+        if (r < k) out[b * k + r] = j;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mlp_gemm(const MlpGemm &g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    dim3 grid((g.M + 31) / 32, (g.N + 31) / 32);
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(64), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *x, uint16_t *y, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, x, y, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bce(const float *S, const uint8_t *Y, int64_t B, int O, float *dS, uint16_t *dS16,
+                      float *row_loss, float *loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(bce_kernel, dim3(unsigned((B + 255) / 256)), dim3(256), 0, s, S, Y, B, O, dS, dS16,
+                       row_loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, row_loss, B, O, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float *dZ, int64_t B, int N, float *db, hipStream_t s)
+{
+    hipLaunchKernelGGL(colsum_kernel, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, dZ, B, N, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_adamw(float *w, const float *g, float *m, float *v, uint16_t *w16, int64_t count,
+                        const MlpAdam &h, const int64_t (&decay)[6], hipStream_t s)
+{
+    hipLaunchKernelGGL(adamw_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, w, g, m, v, w16,
+                       count, h, decay[0], decay[1], decay[2], decay[3], decay[4], decay[5]);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_params(const float *w, uint16_t *w16, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(cast_params_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, w, w16, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const float *S, int64_t B, int O, int k, int32_t *out, hipStream_t s)
+{
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(topk_kernel, dim3(unsigned(B)), dim3(64), 0, s, S, B, O, k, out);
+    return hipGetLastError();
+}
+
+}  // namespace lpb

@@ -107,6 +107,15 @@ struct LP {
     int m, n, N, C, ld, nart;
     int64_t k, ro, co;
     const double *A, *b, *c;
+    const int32_t *rows;  // screened LP: row i is constraint rows[i] of the shared LP
+    int m_full;
+    // Constraint of the (shared) LP that row i reads, clamped into range.
+    __device__ __forceinline__ int row_of(int i) const
+    {
+        if (!rows) return i;
+        const int q = rows[i];
+        return (q >= 0 && q < m_full) ? q : 0;
+    }
     // LDS arrays
     Ctrl<T> *sh;
     int *basis, *nonb, *rowf, *colrow;
@@ -217,7 +226,7 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
     bool bad = false;
     for (int i = wave; i < m; i += W) {
         const double sg = (P.rowf[i] & ROW_NEG) ? -1.0 : 1.0;
-        const double *Ai = P.A + (int64_t)i * n;
+        const double *Ai = P.A + (int64_t)P.row_of(i) * n;
         T *row = tab + (int64_t)i * ld;
         for (int j = lane; j < C; j += 64) {
             double v;
@@ -228,7 +237,7 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
             } else if (j < N) {
                 v = (P.colrow[j - n] == i) ? -1.0 : 0.0;
             } else {
-                v = sg * P.b[i];
+                v = sg * P.b[P.row_of(i)];
             }
             row[j] = T(v);
         }
@@ -241,7 +250,7 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
     }
     if (bad) sh->bad = 1;
     double bmax = 0.0;
-    for (int i = tid; i < m; i += NT) bmax = fmax(bmax, fabs(P.b[i]));
+    for (int i = tid; i < m; i += NT) bmax = fmax(bmax, fabs(P.b[P.row_of(i)]));
     __syncthreads();
     const double cnorm = block_max<T, NT>(cmax, sh);
     const double bnorm = block_max<T, NT>(bmax, sh);
@@ -381,6 +390,32 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
     __syncthreads();
 }
 
+// An LP this launch was not planned for (its index arrays or tableau would
+// not fit the launch's LDS or device-memory slot): reported NUMERICAL
+// without touching the tableau storage.
+template <typename T, int NT>
+__device__ __forceinline__ void reject_lp(const LP<T, NT> &P, const SolveArgs &a)
+{
+    const int tid = threadIdx.x;
+    for (int j = tid; j < P.n; j += NT) a.x[P.co + j] = __builtin_nan("");
+    if (a.basis_out)
+        for (int i = tid; i < P.m; i += NT) a.basis_out[P.ro + i] = -1;
+    if (tid == 0) {
+        a.obj[P.k] = __builtin_nan("");
+        a.status[P.k] = ST_NUMERICAL;
+        if (a.enter_out) a.enter_out[P.k] = -1;
+        if (a.stats) {
+            int32_t *st = a.stats + 8 * P.k;
+            if (a.refine_stats) {
+                st[3] = 1;
+                st[4] = 0;
+            } else {
+                for (int q = 0; q < 8; ++q) st[q] = 0;
+            }
+        }
+    }
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
 {
@@ -407,8 +442,18 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         }
         P.b = a.b + P.ro;
         P.c = a.c + P.co;
-        const int m = P.m, n = P.n;
+        P.rows = nullptr;
+        P.m_full = P.m;
         const int8_t *sense = a.sense + P.ro;
+        if (a.shared) {
+            // One LP's constraints shared by the batch (optionally a row subset of them).
+            P.A = a.A;
+            P.b = a.b;
+            sense = a.sense;
+            P.m_full = a.m_full;
+            P.rows = a.row_subset ? a.row_subset + k * int64_t(P.m) : nullptr;
+        }
+        const int m = P.m, n = P.n;
         LdsLayout L = lds_layout(m, n + m, sizeof(T), sizeof(Ctrl<T>));
         P.sh = sh;
         P.basis = reinterpret_cast<int *>(smem + L.basis);
@@ -417,15 +462,24 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         P.colrow = reinterpret_cast<int *>(smem + L.colrow);
         P.pcol = reinterpret_cast<T *>(smem + L.pcol);
         P.prow = reinterpret_cast<T *>(smem + L.prow);
+        if (L.tab > int64_t(a.lds_bytes)) {
+            reject_lp<T, NT>(P, a);
+            __syncthreads();
+            item = sh->next;
+            __syncthreads();
+            continue;
+        }
 
         // A1: sign-normalise and classify rows (sense after flipping rows with b < 0).
         if (tid == 0) sh->bad = 0;
         __syncthreads();
         bool bad = false;
         for (int i = tid; i < m; i += NT) {
-            const double bi = P.b[i];
-            const int s = sense[i];
+            const int q = P.row_of(i);
+            const double bi = P.b[q];
+            const int s = sense[q];
             bad |= !isfinite(bi) || s < LE || s > EQ;
+            if (P.rows) bad |= P.rows[i] < 0 || P.rows[i] >= P.m_full;
             const bool neg = bi < 0.0;
             int sen = (s < LE || s > EQ) ? LE : s;
             if (neg && sen != EQ) sen = (sen == LE) ? GE : LE;
@@ -457,7 +511,9 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         P.nart = sh->nart;
         const int64_t tab_bytes = int64_t(m + 1) * P.ld * int64_t(sizeof(T));
         const bool in_lds = !a.force_hbm && L.tab + tab_bytes <= int64_t(a.lds_bytes);
-        if (in_lds) {
+        if (!in_lds && (!a.scratch || tab_bytes > a.slot_bytes)) {
+            reject_lp<T, NT>(P, a);
+        } else if (in_lds) {
             P.tab = reinterpret_cast<T *>(smem + L.tab);
             solve_lp<T, NT>(P, a, 3);
         } else {

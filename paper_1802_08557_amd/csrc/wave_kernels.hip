@@ -227,10 +227,11 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
 }
 
 // Bytes of LDS the wave kernel keeps in front of the tableau: the surplus
-// column -> row map, the x staging vector and the LP's objective c.
+// column -> row map, the x staging vector, the LP's objective c and the
+// row -> constraint map of a screened LP.
 __host__ __device__ constexpr int64_t wave_aux_bytes(int rb, int64_t tsize)
 {
-    return align16(4 * 64 * rb) + align16(tsize * 64) + 8 * 64;
+    return align16(4 * 64 * rb) + align16(tsize * 64) + 8 * 64 + 4 * 64 * rb;
 }
 
 // Doubles of A each lane prefetches: LPs with m * n <= 64 * NPF have their
@@ -247,6 +248,8 @@ struct Fetch {
     double av[NPF];  // A in flat row-major order, element lane + 64 t
     double bv[RB];   // b of row lane + 64 r
     int sv[RB];      // sense of row lane + 64 r
+    int rid[RB];     // constraint of the shared LP that row lane + 64 r is (shared only)
+    bool bad_row;    // a row index outside the shared LP (this lane's rows)
     double cv;       // c of column lane
 };
 
@@ -269,15 +272,36 @@ __device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB
         F.co = a.coff[k];
     }
     const int m = F.m, n = F.n;
+    F.bad_row = false;
+    if (a.shared) {
+        // One LP's constraints shared by the batch; a screened LP takes the
+        // rows its subset names (gathered, so A is read row by row later).
+        F.A = a.A;
+        const int32_t *sub = a.row_subset ? a.row_subset + k * int64_t(m) : nullptr;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const int i = lane + 64 * r;
-        F.bv[r] = (i < m) ? a.b[F.ro + i] : 0.0;
-        F.sv[r] = (i < m) ? int(a.sense[F.ro + i]) : 0;
+        for (int r = 0; r < RB; ++r) {
+            const int i = lane + 64 * r;
+            int q = i;
+            if (sub && i < m) q = sub[i];
+            const bool okq = q >= 0 && q < a.m_full;
+            F.bad_row |= i < m && !okq;
+            q = okq ? q : 0;
+            F.rid[r] = q;
+            F.bv[r] = (i < m) ? a.b[q] : 0.0;
+            F.sv[r] = (i < m) ? int(a.sense[q]) : 0;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = lane + 64 * r;
+            F.rid[r] = i;
+            F.bv[r] = (i < m) ? a.b[F.ro + i] : 0.0;
+            F.sv[r] = (i < m) ? int(a.sense[F.ro + i]) : 0;
+        }
     }
     F.cv = (lane < n) ? a.c[F.co + lane] : 0.0;
     const int mn = m * n;
-    F.has_a = mn <= 64 * NPF;
+    F.has_a = mn <= 64 * NPF && !(a.shared && a.row_subset);
     if (F.has_a) {
         // One buffer descriptor over this LP's A: the hardware range check
         // (offset < m*n*8) returns 0 past the end instead of reading further.
@@ -298,6 +322,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
     int *colrow = reinterpret_cast<int *>(smem);
     T *xv = reinterpret_cast<T *>(smem + align16(4 * 64 * RB));
     double *cl = reinterpret_cast<double *>(smem + align16(4 * 64 * RB) + align16(sizeof(T) * 64));
+    int *rowid = reinterpret_cast<int *>(smem + align16(4 * 64 * RB) + align16(sizeof(T) * 64) + 8 * 64);
     const int64_t aux = wave_aux_bytes(RB, sizeof(T));
     const int64_t total = a.num_dev ? int64_t(a.id_base) + *a.num_dev : a.num;
     // Work items: blockIdx.x and blockIdx.x + G first, then 2G + the queue
@@ -320,7 +345,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
         const int m = P.m, n = P.n;
 
         // A1: sign-normalise and classify rows; surplus columns by ballot.
-        bool bad = false;
+        bool bad = F.bad_row;
+        const bool gather = a.shared && a.row_subset;
+        if (gather) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (lane + 64 * r < m) rowid[lane + 64 * r] = F.rid[r];
+        }
         double bv[RB];
         int sc[RB];
         int ng = 0, nart = 0, neq = 0;
@@ -406,10 +437,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
                 constexpr int UB = 16;
                 for (int f0 = 0; f0 < mn; f0 += 64 * UB) {
                     double av[UB];
+                    if (gather) {
+                        // Row f / n of the LP is constraint rowid[f / n] of the shared LP.
+                        int rr = ri, cc = cj2;
 #pragma unroll
-                    for (int u = 0; u < UB; ++u) {
-                        const int f = f0 + 64 * u + lane;
-                        av[u] = (f < mn) ? P.A[f] : 0.0;
+                        for (int u = 0; u < UB; ++u) {
+                            const int f = f0 + 64 * u + lane;
+                            av[u] = 0.0;
+                            if (f < mn) av[u] = P.A[int64_t(rowid[rr < m ? rr : m - 1]) * n + cc];
+                            rr += dq;
+                            cc += dr;
+                            if (cc >= n) { cc -= n; ++rr; }
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            const int f = f0 + 64 * u + lane;
+                            av[u] = (f < mn) ? P.A[f] : 0.0;
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < UB; ++u) {
@@ -589,6 +634,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
     }
     if (lane == 0) finish_launch(a.queue, a.done, a.reset_extra);
 }
+
 
 template <typename T, int RB>
 hipError_t launch_t(const SolveArgs &a, int grid, hipStream_t s)

@@ -20,13 +20,17 @@ LP_LE, LP_GE, LP_EQ = 0, 1, 2
 OPTIMAL, INFEASIBLE, UNBOUNDED, ITERATION_LIMIT, NUMERICAL, INVALID_INPUT = range(6)
 PREC_FP64, PREC_FP32_CERT64 = 0, 1
 PLACE_AUTO, PLACE_LDS, PLACE_HBM = 0, 1, 2
-FLAG_SYNC, FLAG_TIME_KERNELS = 1, 2
+FLAG_SYNC, FLAG_TIME_KERNELS, FLAG_AUTOTUNE = 1, 2, 4
 STATS_WIDTH = 8
 LP_OK, LP_ERR_ARG, LP_ERR_NOMEM, LP_ERR_HIP = 0, -1, -2, -3
 
 # Every symbol include/lpbatch.h declares.
 EXPORTS = ("lp_batch_solve", "lp_ctx_create", "lp_ctx_destroy", "lp_options_init",
-           "lp_batch_solve_ex", "lp_ctx_kernel_times", "lp_last_error")
+           "lp_batch_solve_ex", "lp_ctx_kernel_times", "lp_last_error",
+           "lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
+           "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
+           "lp_hyperbox_support", "lp_ctx_tuning")
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NUM_PARAMS = 20, 256, 120, 102008
 
 
 class LPOptions(ctypes.Structure):
@@ -35,7 +39,8 @@ class LPOptions(ctypes.Structure):
                 ("tol_feas", ctypes.c_double), ("k_deg", ctypes.c_int32),
                 ("placement", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("stats", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("shared", ctypes.c_int32),
+                ("row_subset", ctypes.c_void_p), ("subset_m", ctypes.c_int32)]
 
 
 class LPBatchError(RuntimeError):
@@ -72,6 +77,22 @@ def load():
     lib.lp_ctx_kernel_times.restype = i32
     lib.lp_last_error.argtypes = []
     lib.lp_last_error.restype = ctypes.c_char_p
+    lib.lp_mlp_init.argtypes = [vp, ctypes.c_uint64]
+    lib.lp_mlp_set_params.argtypes = [vp, vp, vp]
+    lib.lp_mlp_get_params.argtypes = [vp, vp, vp]
+    lib.lp_mlp_infer.argtypes = [vp, i64, vp, vp, vp, ctypes.c_int32, vp]
+    lib.lp_mlp_grads.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    lib.lp_mlp_train_step.argtypes = [vp, i64, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp]
+    lib.lp_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    lib.lp_mlp_load.argtypes = [vp, ctypes.c_char_p]
+    lib.lp_hyperbox_support.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+    lib.lp_hyperbox_support.restype = i32
+    lib.lp_ctx_tuning.argtypes = [vp, vp, i32]
+    lib.lp_ctx_tuning.restype = i32
+    for nm in ("lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
+               "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
+           "lp_hyperbox_support", "lp_ctx_tuning"):
+        getattr(lib, nm).restype = i32
     _lib = lib
     return lib
 
@@ -90,6 +111,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _require(t, dtype, numel):
+    """A contiguous device tensor of the given dtype and element count."""
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != f"torch.{dtype}" or t.numel() != numel:
+        raise ValueError(f"expected a contiguous {dtype} device tensor of {numel} elements, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+
 @dataclass
 class DeviceBatch:
     """A batch resident on the GPU: A, b, c (float64), sense (int8) as torch
@@ -105,6 +133,8 @@ class DeviceBatch:
     def num_lps(self):
         return int(self.m.shape[0])
 
+    shared: bool = False  # A, b, sense hold one LP used by every LP of the batch
+
     @classmethod
     def from_host(cls, batch, device="cuda"):
         import torch
@@ -112,6 +142,17 @@ class DeviceBatch:
         return cls(t(batch.A, np.float64), t(batch.b, np.float64), t(batch.c, np.float64),
                    t(batch.sense, np.int8), np.ascontiguousarray(batch.m, np.int32),
                    np.ascontiguousarray(batch.n, np.int32))
+
+    @classmethod
+    def shared_from_host(cls, A, b, sense, c, device="cuda"):
+        """N LPs over one constraint set: A [m, n], b [m], sense [m]; c [N, n]."""
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        A = np.asarray(A)
+        N = int(np.asarray(c).shape[0])
+        m, n = A.shape
+        return cls(t(A.reshape(-1), np.float64), t(b, np.float64), t(np.asarray(c).reshape(-1), np.float64),
+                   t(sense, np.int8), np.full(N, m, np.int32), np.full(N, n, np.int32), shared=True)
 
 
 @dataclass
@@ -145,8 +186,11 @@ class Context:
 
     def solve(self, batch: DeviceBatch, *, precision=PREC_FP64, max_iters=0, tol_piv=0.0,
               tol_opt=0.0, tol_feas=0.0, k_deg=50, placement=PLACE_AUTO, block_threads=0,
-              stats=False, stream=None, sync=False, time_kernels=False, out=None) -> Solution:
-        """Queue lp_batch_solve_ex on `stream` (default: torch's current stream)."""
+              stats=False, stream=None, sync=False, time_kernels=False, out=None,
+              row_subset=None, autotune=False) -> Solution:
+        """Queue lp_batch_solve_ex on `stream` (default: torch's current stream).
+        row_subset: int32 device tensor [N, subset_m] for a screened solve of a
+        shared batch."""
         import torch
         dev = batch.A.device
         N = batch.num_lps
@@ -166,7 +210,15 @@ class Context:
         o.k_deg, o.placement, o.block_threads = k_deg, placement, block_threads
         o.stats = st.data_ptr() if st is not None else None
         o.stream = ctypes.c_void_p(stream.cuda_stream)
-        o.flags = (FLAG_SYNC if sync else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
+        o.flags = ((FLAG_SYNC if sync else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
+                   | (FLAG_AUTOTUNE if autotune else 0))
+        o.shared = 1 if batch.shared else 0
+        if row_subset is not None:
+            if row_subset.dim() != 2 or row_subset.shape[0] != N:
+                raise ValueError("row_subset must be [num_lps, subset_m]")
+            _require(row_subset, "int32", row_subset.numel())
+            o.row_subset = row_subset.data_ptr()
+            o.subset_m = int(row_subset.shape[1])
         m = np.ascontiguousarray(batch.m, np.int32)
         n = np.ascontiguousarray(batch.n, np.int32)
         _check(self.lib.lp_batch_solve_ex(
@@ -174,6 +226,92 @@ class Context:
             m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
             _ptr(status), _ptr(x), _ptr(obj), ctypes.byref(o)))
         return Solution(status, x, obj, st)
+
+    # Warm-start network (lp_mlp_*): tensors are torch tensors on this device.
+    def _stream(self, stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def mlp_init(self, seed: int):
+        _check(self.lib.lp_mlp_init(self.handle, ctypes.c_uint64(seed)))
+
+    def mlp_set_params(self, params, stream=None):
+        """params: float32 [MLP_NUM_PARAMS] device tensor (copied)."""
+        _require(params, "float32", MLP_NUM_PARAMS)
+        _check(self.lib.lp_mlp_set_params(self.handle, _ptr(params), self._stream(stream)))
+
+    def mlp_get_params(self, stream=None):
+        import torch
+        out = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(self.lib.lp_mlp_get_params(self.handle, _ptr(out), self._stream(stream)))
+        return out
+
+    def mlp_infer(self, dirs, k=0, scores=True, stream=None):
+        """dirs: float32 [B, 20] device tensor.  Returns (scores [B, 120] or
+        None, top_k [B, k] int32 or None)."""
+        import torch
+        B = int(dirs.shape[0])
+        _require(dirs, "float32", B * MLP_IN)
+        dev = dirs.device
+        S = torch.empty((B, MLP_OUT), dtype=torch.float32, device=dev) if scores else None
+        T = torch.empty((B, k), dtype=torch.int32, device=dev) if k else None
+        _check(self.lib.lp_mlp_infer(self.handle, B, _ptr(dirs), _ptr(S), _ptr(T), int(k),
+                                     self._stream(stream)))
+        return S, T
+
+    def mlp_grads(self, dirs, tight, stream=None):
+        """Returns (grad float32 [MLP_NUM_PARAMS], loss float32 [1]) device tensors."""
+        import torch
+        B = int(dirs.shape[0])
+        _require(dirs, "float32", B * MLP_IN)
+        _require(tight, "uint8", B * MLP_OUT)
+        g = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device=dirs.device)
+        L = torch.empty(1, dtype=torch.float32, device=dirs.device)
+        _check(self.lib.lp_mlp_grads(self.handle, B, _ptr(dirs), _ptr(tight), _ptr(g), _ptr(L),
+                                     self._stream(stream)))
+        return g, L
+
+    def mlp_train_step(self, dirs, tight, lr, weight_decay=0.0, loss=None, stream=None):
+        """One AdamW step; the loss before it goes to `loss` (float32 [1] device
+        tensor) when given."""
+        B = int(dirs.shape[0])
+        _require(dirs, "float32", B * MLP_IN)
+        _require(tight, "uint8", B * MLP_OUT)
+        _check(self.lib.lp_mlp_train_step(self.handle, B, _ptr(dirs), _ptr(tight), float(lr),
+                                          float(weight_decay), _ptr(loss), self._stream(stream)))
+
+    def mlp_save(self, path: str):
+        _check(self.lib.lp_mlp_save(self.handle, os.fsencode(path)))
+
+    def mlp_load(self, path: str):
+        _check(self.lib.lp_mlp_load(self.handle, os.fsencode(path)))
+
+    def hyperbox_support(self, lo, hi, l, want_x=False, stream=None):
+        """Closed-form box LPs: l float64 [num, n]; lo, hi float64 [num, n] or
+        [n] (one box for every direction).  Returns (value [num], x or None)."""
+        import torch
+        num, n = int(l.shape[0]), int(l.shape[1])
+        shared_box = lo.dim() == 1
+        _require(l, "float64", num * n)
+        _require(lo, "float64", n if shared_box else num * n)
+        _require(hi, "float64", n if shared_box else num * n)
+        value = torch.empty(num, dtype=torch.float64, device=l.device)
+        x = torch.empty((num, n), dtype=torch.float64, device=l.device) if want_x else None
+        _check(self.lib.lp_hyperbox_support(self.handle, num, n, _ptr(lo), _ptr(hi), _ptr(l),
+                                            1 if shared_box else 0, _ptr(value), _ptr(x),
+                                            self._stream(stream)))
+        return value, x
+
+    def tuning(self):
+        """[(bin, fp32, workgroup size, hbm)] of the context's autotuned launches."""
+        cnt = self.lib.lp_ctx_tuning(self.handle, None, 0)
+        if cnt < 0:
+            raise LPBatchError(cnt, last_error())
+        buf = (ctypes.c_int32 * (4 * max(cnt, 1)))()
+        self.lib.lp_ctx_tuning(self.handle, buf, cnt)
+        return [tuple(buf[4 * i:4 * i + 4]) for i in range(cnt)]
 
     def kernel_times(self, cap=4096):
         """[(name, ms)] of every kernel of the solves made with time_kernels=True
