@@ -220,6 +220,16 @@ def warm_start_block(args):
                          resolved_fp64=int(np.sum(stats[:, 3] == 1)),
                          status_match=int(np.sum(stn[:ns] == ref.status)), compared=int(ns),
                          max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
+    # The network's share of the warm step: inference + top-k alone.
+    warmstart.screen(ctx, d_eval, K)
+    torch.cuda.synchronize()
+    st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.record(stream)
+    for _ in range(args.warm_steps):
+        warmstart.screen(ctx, d_eval, K)
+    sp.record(stream)
+    torch.cuda.synchronize()
+    res["warm_fp32_cert"]["mlp_infer_topk_ms"] = st.elapsed_time(sp) / args.warm_steps
     base = res["plain_fp64"]["lps_per_s"]
     for name in res:
         res[name]["speedup_vs_plain_fp64"] = res[name]["lps_per_s"] / base
@@ -242,6 +252,10 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start comparison")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the size-binned launches on the first (untimed) solve")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one solve in a HIP graph and time its replays")
     ap.add_argument("--warm-only", action="store_true", help="print only the warm-start comparison")
     ap.add_argument("--warm-lps", type=int, default=100_000)
     ap.add_argument("--warm-train", type=int, default=200_000)
@@ -271,11 +285,29 @@ def main():
     stream = torch.cuda.current_stream()
     N = batch.num_lps
     prec = lpbatch.PREC_FP64 if args.precision == "fp64" else lpbatch.PREC_FP32_CERT64
-    out = ctx.solve(db, stats=True, stream=stream, precision=prec)  # allocates outputs once
+    # allocates outputs once (and tunes the size bins when asked)
+    out = ctx.solve(db, stats=True, stream=stream, precision=prec, autotune=args.autotune)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         ctx.solve(db, stats=True, stream=stream, out=out, precision=prec)
     torch.cuda.synchronize()
+
+    graph = None
+    if args.graph:
+        # One solve captured on a side stream; its kernels' counters reset
+        # themselves, so every replay is a full solve.
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            ctx.solve(db, stats=True, out=out, precision=prec)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            ctx.solve(db, stats=True, out=out, precision=prec)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
 
     ctx.kernel_times()  # forget warm-up timings
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -283,12 +315,19 @@ def main():
     t_wall = time.perf_counter()
     start.record(stream)
     for _ in range(args.steps):
-        ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True, precision=prec)
+        if graph is not None:
+            graph.replay()
+        else:
+            ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True, precision=prec)
     stop.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     total_ms = start.elapsed_time(stop)
     ms_per_step = total_ms / args.steps
+    if graph is not None:
+        # Per-kernel times from one timed eager solve after the replays.
+        ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True, precision=prec)
+        torch.cuda.synchronize()
 
     per_kernel = {}
     for nm, v in ctx.kernel_times():
@@ -326,7 +365,10 @@ def main():
                config=dict(workload=batch.name, num_lps=N, m=int(batch.m.max()),
                            n=int(batch.n.max()), precision=args.precision,
                            seed=batch.meta.get("seed"), placement="lds" if lds_resident else "hbm"),
-               roofline=roof, kernels_ms=per_kernel, wall_s=t_wall)
+               roofline=roof, kernels_ms=per_kernel, wall_s=t_wall,
+               launch="hip_graph_replay" if graph is not None else "eager")
+    if args.autotune:
+        rec["tuning"] = [dict(bin=b, fp32=f, threads=t, hbm=h) for b, f, t, h in ctx.tuning()]
     if not args.no_cpu:
         ref, cb = cpu_baseline(batch)
         rec["cpu_baseline"] = cb

@@ -125,8 +125,11 @@ typedef struct {
     double tol_feas;     /* Phase I optimum threshold, relative to 1 + |b|_inf   */
     int32_t k_deg;       /* degenerate pivots before Bland's rule; 0: 50; <0: off */
     int32_t placement;   /* 0 auto, LP_PLACE_LDS or LP_PLACE_HBM (HBM: every LP's
-                            tableau in a device scratch slot, workgroup kernel)   */
-    int32_t block_threads; /* 0 auto: LPs of <= 63 columns and <= 128 rows get one
+                            tableau in a device scratch slot, workgroup kernel).
+                            Auto keeps a workgroup-kernel tableau in LDS when it
+                            takes at most a third of a CU's LDS; LP_PLACE_LDS
+                            whenever it fits                                       */
+    int32_t block_threads; /* 0 auto: LPs of <= 64 columns and <= 128 rows get one
                             wavefront each, others a workgroup; 64, 128, 256 or
                             512: every LP gets a workgroup of that many threads  */
     int32_t *stats;      /* optional DEVICE int32 [num_lps][LP_STATS_WIDTH]       */

@@ -482,19 +482,17 @@ __device__ __forceinline__ bool wave_all(bool v) { return __ballot(!v) == 0; }
 // per step with readlane.  W wavefronts share a workgroup, each with its own
 // LP and LDS region; with stage_a the shared constraint matrix is copied into
 // LDS once per workgroup and every A access of the certificate hits LDS.
-template <int W>
+template <int W, bool STAGE>
 __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t off = 0;
-    const double *Astage = nullptr;
-    if (a.stage_a) {
+    if constexpr (STAGE) {
         double *As = reinterpret_cast<double *>(smem);
         const int64_t cnt = int64_t(a.um) * a.un;
         for (int64_t e = threadIdx.x; e < cnt; e += 64 * W) As[e] = a.A[e];
         __syncthreads();
-        Astage = As;
         off = align16(8 * cnt);
     }
     char *my = smem + off + int64_t(wave) * a.wave_bytes;
@@ -511,13 +509,15 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
         } else {
             m = a.m[k]; n = a.n[k]; ao = a.aoff[k]; ro = a.roff[k]; co = a.coff[k];
         }
-        const double *A = a.A + ao, *b = a.b + ro, *c = a.c + co;
+        // A stays in one address space per instantiation (LDS when staged),
+        // so its loads compile to LDS or global instructions, not flat ones.
+        const double *A = STAGE ? reinterpret_cast<const double *>(smem) : a.A + (a.shared ? 0 : ao);
+        const double *b = a.b + ro, *c = a.c + co;
         const int8_t *sense = a.sense + ro;
         const int32_t *basis = a.basis + ro;
         const int32_t *sub = nullptr;
         int ms = m;
         if (a.shared) {
-            A = Astage ? Astage : a.A;
             b = a.b;
             sense = a.sense;
             if (a.row_subset) {
@@ -599,42 +599,64 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
             const double bnorm = wave_max(bm), cnorm = wave_max(cm);
             const double tol_p = a.tol_feas * (1.0 + bnorm);
             const double tol_d = a.tol_opt * fmax(1.0, cnorm);
-            bool ok = kt == K && K <= 64 && __ballot(bad) == 0;
-            double *M = (K <= a.kl) ? reinterpret_cast<double *>(my + L.mat)
-                                    : reinterpret_cast<double *>(a.scratch + (int64_t(blockIdx.x) * W + wave) *
-                                                                              a.slot_bytes);
-            // Lane t: row t of B_TS (column-major, M[s*K + t]) and its rhs; lane
-            // j: c of the j-th basic structural.
+            // A basis with more than kl basic structurals (rare: the host sizes kl
+            // for the batch) is left to the FP64 re-solve.
+            bool ok = kt == K && K <= a.kl && __ballot(bad) == 0;
+            double *M = reinterpret_cast<double *>(my + L.mat);
+            // Lane t holds the t-th tight row (index and sign) and lane s the
+            // s-th basic structural, so loops over T or S read them with
+            // readlane instead of LDS.  M is B_TS column-major (M[s*K + t],
+            // row t in lane t); every loop over M loads eight entries ahead.
+            const bool kfit = K <= a.kl;
+            const int tl = (lane < K && kfit) ? tlist[lane] : 0;
+            const int sl = (lane < K && kfit) ? slist[lane] : 0;
+            const double sgt = (lane < K && kfit && (rowf[tl] & kRowNeg)) ? -1.0 : 1.0;
+            const int lk = lane < K ? lane : 0;  // an in-range row of M for idle lanes
             double rz = 0.0, cs = 0.0;
             int pos = kBig;  // step at which this lane's row became the pivot row
+            int ordr = 0;    // lane p: the row chosen at step p
             if (ok) {
                 double am = 0.0;
-                if (lane < K) {
-                    const int i = tlist[lane];
-                    const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
-                    const double *Ai = A + int64_t(i) * n;
-                    for (int s2 = 0; s2 < K; ++s2) {
-                        const double v = sg * Ai[slist[s2]];
-                        M[s2 * K + lane] = v;
-                        am = fmax(am, fabs(v));
-                    }
-                    rz = sg * b[i];
-                    cs = c[slist[lane]];
+                const double *At = A + int64_t(tl) * n;
+                for (int s0 = 0; s0 < K; s0 += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v[q] = (s0 + q < K) ? sgt * At[lane_get(sl, s0 + q < K ? s0 + q : 0)] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (s0 + q < K && lane < K) {
+                            M[(s0 + q) * K + lane] = v[q];
+                            am = fmax(am, fabs(v[q]));
+                        }
                 }
+                rz = (lane < K) ? sgt * b[tl] : 0.0;
+                cs = (lane < K) ? c[sl] : 0.0;
                 const double amax = wave_max(am);
                 wave_sync();
                 for (int p = 0; p < K; ++p) {
-                    const double v = (lane < K && pos == kBig) ? fabs(M[p * K + lane]) : -1.0;
+                    const double v = (lane < K && pos == kBig) ? fabs(M[p * K + lk]) : -1.0;
                     const double vmax = wave_max(v);
                     if (!(vmax > 1e-13 * fmax(1.0, amax))) { ok = false; break; }
                     const int pl = __builtin_ctzll(__ballot(v == vmax));
                     if (lane == pl) pos = p;
+                    if (lane == p) ordr = pl;
                     if (lane == 0) order[p] = pl;
-                    const double u = M[p * K + pl];
-                    if (lane < K && pos == kBig) {
-                        const double l = M[p * K + lane] / u;
-                        M[p * K + lane] = l;
-                        for (int j = p + 1; j < K; ++j) M[j * K + lane] = fma(-l, M[j * K + pl], M[j * K + lane]);
+                    const double uinv = 1.0 / M[p * K + pl];
+                    const bool act = lane < K && pos == kBig;
+                    const int la = act ? lane : pl;
+                    const double l = M[p * K + la] * uinv;
+                    if (act) M[p * K + lane] = l;
+                    for (int j0 = p + 1; j0 < K; j0 += 8) {
+                        double pr[8], mr[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int j = j0 + q < K ? j0 + q : K - 1;
+                            pr[q] = M[j * K + pl];
+                            mr[q] = M[j * K + la];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (j0 + q < K && act) M[(j0 + q) * K + lane] = fma(-l, pr[q], mr[q]);
                     }
                     wave_sync();
                 }
@@ -642,54 +664,84 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
             }
             double xr = 0.0;  // lane p: x of the p-th basic structural
             if (ok) {
-                // x_S: L z = P b_T (lane-per-row), then U x = z.
-                for (int p = 0; p < K; ++p) {
-                    const double zp = lane_get(rz, order[p]);
-                    if (lane < K && pos > p) rz = fma(-M[p * K + lane], zp, rz);
+                // x_S (L z = P b_T, then U x = z) and y_T (U^T w = c_S, then
+                // L^T v = w, y_t = v[pos_t]) side by side, so the two chains of
+                // dependent steps overlap; lane p keeps 1 / U_pp.
+                double rinv = 0.0, wr = 0.0;
+                for (int p0 = 0; p0 < K; p0 += 8) {
+                    double mv[8], mu[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int p = p0 + q < K ? p0 + q : K - 1;
+                        mv[q] = M[p * K + lk];                 // lane t: L[t][p] (rows below p)
+                        mu[q] = M[lk * K + lane_get(ordr, p)]; // lane j: U[p][j]
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int p = p0 + q;
+                        if (p < K) {
+                            const double zp = lane_get(rz, lane_get(ordr, p));
+                            if (lane < K && pos > p) rz = fma(-mv[q], zp, rz);
+                            const double ip = 1.0 / lane_get(mu[q], p);
+                            if (lane == p) rinv = ip;
+                            const double wp = lane_get(cs, p) * ip;
+                            if (lane == p) wr = wp;
+                            if (lane > p && lane < K) cs = fma(-mu[q], wp, cs);
+                        }
+                    }
                 }
-                for (int p = K - 1; p >= 0; --p) {
-                    const int pl = order[p];
-                    const double xp = lane_get(rz, pl) / M[p * K + pl];
-                    if (lane == p) xr = xp;
-                    if (lane < K && pos < p) rz = fma(-M[p * K + lane], xp, rz);
+                for (int h = K - 1; h >= 0; h -= 8) {
+                    double mv[8], ml[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int p = h - q >= 0 ? h - q : 0;
+                        mv[q] = M[p * K + lk];                 // lane t: U[pos_t][p]
+                        ml[q] = M[lk * K + lane_get(ordr, p)]; // lane p': L[p][p']
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int p = h - q;
+                        if (p >= 0) {
+                            const int pl = lane_get(ordr, p);
+                            const double xp = lane_get(rz, pl) * lane_get(rinv, p);
+                            if (lane == p) xr = xp;
+                            if (lane < K && pos < p) rz = fma(-mv[q], xp, rz);
+                            const double vq = lane_get(wr, p);
+                            if (lane < p) wr = fma(-ml[q], vq, wr);
+                        }
+                    }
                 }
                 if (lane < K) xsv[lane] = xr;
-                // y_T: U^T w = c_S, L^T v = w (lane-per-position), y_t = v[pos_t].
-                double wr = 0.0;
-                for (int p = 0; p < K; ++p) {
-                    const int pl = order[p];
-                    const double wp = lane_get(cs, p) / M[p * K + pl];
-                    if (lane == p) wr = wp;
-                    if (lane > p && lane < K) cs = fma(-M[lane * K + pl], wp, cs);
-                }
-                for (int q = K - 1; q >= 0; --q) {
-                    const double vq = lane_get(wr, q);
-                    const int oq = order[q];
-                    if (lane < q) wr = fma(-M[lane * K + oq], vq, wr);
-                }
                 const double yt = __shfl(wr, pos < 64 ? pos : 0);
+                const double ysg = yt * sgt;  // dual times the row's sign
                 if (lane < K) yv[lane] = yt;
                 wave_sync();
 
-                // Primal certificate.
+                // Primal certificate: every non-tight row's slack from x_S.
                 bool pf = !(lane < K) || xr >= -tol_p;
-                for (int i = lane; i < m; i += 64) {
-                    const int f = rowf[i];
-                    if (f & kTight) continue;
-                    const double *Ai = A + int64_t(i) * n;
-                    double ax0 = 0.0, ax1 = 0.0;
-                    int s2 = 0;
-                    for (; s2 + 1 < K; s2 += 2) {
-                        ax0 = fma(Ai[slist[s2]], xsv[s2], ax0);
-                        ax1 = fma(Ai[slist[s2 + 1]], xsv[s2 + 1], ax1);
+                for (int i0 = 0; i0 < m; i0 += 64) {
+                    const int i = i0 + lane;
+                    const int f = (i < m) ? rowf[i] : kTight;
+                    const bool act = !(f & kTight);
+                    const double *Ai = A + int64_t(act ? i : 0) * n;
+                    double ax[4] = {0.0, 0.0, 0.0, 0.0};
+                    for (int s0 = 0; s0 < K; s0 += 8) {
+                        double av[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) av[q] = Ai[lane_get(sl, s0 + q < K ? s0 + q : 0)];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (s0 + q < K) ax[q & 3] = fma(av[q], lane_get(xr, s0 + q), ax[q & 3]);
                     }
-                    if (s2 < K) ax0 = fma(Ai[slist[s2]], xsv[s2], ax0);
-                    const double sg = (f & kRowNeg) ? -1.0 : 1.0;
-                    const double r = sg * (b[i] - (ax0 + ax1));
-                    const int sen = (f >> 1) & 3;
-                    if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;  // a row left out of a screened solve can be an equality
-                    else if (sen == kLE) pf &= r >= -tol_p;
-                    else if (sen == kGE) pf &= -r >= -tol_p;
+                    if (act) {
+                        const double sg = (f & kRowNeg) ? -1.0 : 1.0;
+                        const double r = sg * (b[i] - ((ax[0] + ax[1]) + (ax[2] + ax[3])));
+                        const int sen = (f >> 1) & 3;
+                        // A row left out of a screened solve can be an equality.
+                        if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;
+                        else if (sen == kLE) pf &= r >= -tol_p;
+                        else if (sen == kGE) pf &= -r >= -tol_p;
+                    }
                 }
                 const bool primal_ok = wave_all(pf);
                 if (primal_ok) cert |= LP_CERT_PRIMAL_OK_BIT;
@@ -697,26 +749,24 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 if (st0 == kOptimal && primal_ok) {
                     // Dual certificate: reduced costs of every non-basic column.
                     bool df = true;
-                    for (int j = lane; j < n; j += 64) {
-                        if (spos[j] >= 0) continue;
-                        double ya0 = 0.0, ya1 = 0.0;
-                        int t = 0;
-                        for (; t + 1 < K; t += 2) {
-                            const int i0 = tlist[t], i1 = tlist[t + 1];
-                            const double s0 = (rowf[i0] & kRowNeg) ? -1.0 : 1.0;
-                            const double s1 = (rowf[i1] & kRowNeg) ? -1.0 : 1.0;
-                            ya0 = fma(yv[t], s0 * A[int64_t(i0) * n + j], ya0);
-                            ya1 = fma(yv[t + 1], s1 * A[int64_t(i1) * n + j], ya1);
+                    for (int j0 = 0; j0 < n; j0 += 64) {
+                        const int j = j0 + lane;
+                        const bool act = j < n && spos[j] < 0;
+                        const int jc = act ? j : 0;
+                        double ya[4] = {0.0, 0.0, 0.0, 0.0};
+                        for (int t0 = 0; t0 < K; t0 += 8) {
+                            double av[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q)
+                                av[q] = A[int64_t(lane_get(tl, t0 + q < K ? t0 + q : 0)) * n + jc];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q)
+                                if (t0 + q < K) ya[q & 3] = fma(lane_get(ysg, t0 + q), av[q], ya[q & 3]);
                         }
-                        if (t < K) {
-                            const int i0 = tlist[t];
-                            const double s0 = (rowf[i0] & kRowNeg) ? -1.0 : 1.0;
-                            ya0 = fma(yv[t], s0 * A[int64_t(i0) * n + j], ya0);
-                        }
-                        df &= c[j] - (ya0 + ya1) <= tol_d;
+                        if (act) df &= c[j] - ((ya[0] + ya[1]) + (ya[2] + ya[3])) <= tol_d;
                     }
                     if (lane < K) {
-                        const int sen = (rowf[tlist[lane]] >> 1) & 3;
+                        const int sen = (rowf[tl] >> 1) & 3;
                         if (sen == kLE) df &= -yt <= tol_d;
                         else if (sen == kGE) df &= yt <= tol_d;
                     }
@@ -851,30 +901,31 @@ hipError_t launch_certify(int nt, const CertArgs &a, int grid, hipStream_t s)
 int certify_blocks_per_cu(int nt, int lds) { return nt == 64 ? occ_t<64>(lds) : occ_t<256>(lds); }
 
 namespace {
-template <int W>
+template <int W, bool STAGE>
 hipError_t launch_w(const CertArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((certify_wave_kernel<W>), dim3(grid), dim3(64 * W), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((certify_wave_kernel<W, STAGE>), dim3(grid), dim3(64 * W), a.lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool STAGE>
 int occ_w(int lds)
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)certify_wave_kernel<W>, 64 * W, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)certify_wave_kernel<W, STAGE>, 64 * W,
+                                                     lds) != hipSuccess)
         return 0;
     return blocks;
 }
 }  // namespace
 
+// waves = 1: A read from device memory; 8 or 16: the shared A staged in LDS.
 hipError_t launch_certify_wave(int waves, const CertArgs &a, int grid, hipStream_t s)
 {
     switch (waves) {
-    case 1: return launch_w<1>(a, grid, s);
-    case 8: return launch_w<8>(a, grid, s);
-    case 16: return launch_w<16>(a, grid, s);
+    case 1: return launch_w<1, false>(a, grid, s);
+    case 8: return launch_w<8, true>(a, grid, s);
+    case 16: return launch_w<16, true>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -882,9 +933,9 @@ hipError_t launch_certify_wave(int waves, const CertArgs &a, int grid, hipStream
 int certify_wave_blocks_per_cu(int waves, int lds)
 {
     switch (waves) {
-    case 1: return occ_w<1>(lds);
-    case 8: return occ_w<8>(lds);
-    case 16: return occ_w<16>(lds);
+    case 1: return occ_w<1, false>(lds);
+    case 8: return occ_w<8, true>(lds);
+    case 16: return occ_w<16, true>(lds);
     default: return 0;
     }
 }
@@ -892,8 +943,8 @@ int certify_wave_blocks_per_cu(int waves, int lds)
 hipError_t certify_configure(int max_lds)
 {
     const void *fns[] = {(const void *)certify_kernel<64>, (const void *)certify_kernel<256>,
-                         (const void *)certify_wave_kernel<1>, (const void *)certify_wave_kernel<8>,
-                         (const void *)certify_wave_kernel<16>};
+                         (const void *)certify_wave_kernel<1, false>, (const void *)certify_wave_kernel<8, true>,
+                         (const void *)certify_wave_kernel<16, true>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;

@@ -87,7 +87,7 @@ struct MlpState {
 // Tuned launch of one size bin of the workgroup kernel.
 struct TuneEntry {
     int nt;         // workgroup size
-    int force_hbm;  // 1: tableaux in device-memory slots even when LDS would hold them
+    int force_hbm;  // 1: tableaux in device-memory slots; 0: in LDS whenever they fit
 };
 
 inline int tune_key(int bin, bool fp32) { return bin * 2 + (fp32 ? 1 : 0); }

@@ -161,11 +161,14 @@ int64_t simplex_ctrl_bytes(bool fp32);
 // Allows every simplex kernel instantiation up to max_lds bytes of dynamic LDS.
 hipError_t simplex_configure(int max_lds);
 
-// One-wavefront-per-LP kernel (wave_kernels.hip) for LPs of at most 63
+// One-wavefront-per-LP kernel (wave_kernels.hip) for LPs of at most 64
 // non-basic columns and 64*rb rows (rb = 1 or 2).
-hipError_t launch_simplex_wave(bool fp32, int rb, const SolveArgs &a, int grid, hipStream_t s);
-int simplex_wave_blocks_per_cu(bool fp32, int rb, int lds_bytes);
-int64_t wave_lds_aux_bytes(int rb, bool fp32);
+// pf: the instantiation that prefetches each next LP's A into registers
+// (LPs of at most wave_prefetch_elems() entries, A not row-gathered).
+hipError_t launch_simplex_wave(bool fp32, int rb, bool pf, const SolveArgs &a, int grid, hipStream_t s);
+int simplex_wave_blocks_per_cu(bool fp32, int rb, bool pf, int lds_bytes);
+int wave_prefetch_elems();
+int64_t wave_lds_aux_bytes(int rb, bool gather);
 // LDS bytes of a column-major wavefront tableau with m rows and `cols` columns.
 int64_t wave_tab_bytes(int m, int cols, bool fp32);
 hipError_t simplex_wave_configure(int max_lds);

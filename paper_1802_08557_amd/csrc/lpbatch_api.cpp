@@ -59,10 +59,10 @@ struct PassCounters {
     int32_t *defer;    // LPs deferred by the wavefront kernel
 };
 
-bool wave_fit(const lp_ctx *ctx, int64_t mk, int64_t nk, bool fp32)
+bool wave_fit(const lp_ctx *ctx, int64_t mk, int64_t nk, bool fp32, bool gather)
 {
-    return nk <= 63 && mk <= 128 &&
-           lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, fp32) + lpb::wave_tab_bytes(int(mk), int(nk) + 1, fp32) <=
+    return nk <= 64 && mk <= 128 &&
+           lpb::wave_lds_aux_bytes(mk > 64 ? 2 : 1, gather) + lpb::wave_tab_bytes(int(mk), int(nk), fp32) <=
                ctx->max_lds;
 }
 
@@ -70,6 +70,15 @@ bool wave_fit(const lp_ctx *ctx, int64_t mk, int64_t nk, bool fp32)
 // host-built id lists already on the device (wave_ids, and block ids at the
 // front of defer_ids), or -- when list_count is set -- the device list
 // list_ids[0 .. *list_count), all offered to the wavefront kernel first.
+// LDS a workgroup-kernel tableau may take.  By default at most a third of
+// the CU's LDS, so that three or more workgroups share a CU and hide each
+// other's latency; a larger tableau streams from its device-memory slot
+// instead.  LP_PLACE_LDS asks for LDS whenever the tableau fits at all.
+int64_t lds_budget(const lp_ctx *ctx, int placement)
+{
+    return placement == LP_PLACE_LDS ? ctx->max_lds : ctx->max_lds / 3;
+}
+
 // One persistent launch of the wavefront kernel over ids[0 .. num) (or the
 // device list ids[0 .. *list_count)); LPs it cannot take are appended to
 // defer_ids from defer_base on.
@@ -90,13 +99,19 @@ int launch_wave(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, PassCounters pc
     w.defer_count = pc.defer;
     w.defer_base = defer_base;
     // Budget for the common case of no surplus columns; an LP needing more is deferred.
-    const int64_t lds = lpb::wave_lds_aux_bytes(rb, fp32) + lpb::wave_tab_bytes(wm_max, wn_max + 1, fp32);
+    const bool gather = a.shared && a.row_subset;
+    const int64_t lds = lpb::wave_lds_aux_bytes(rb, gather) + lpb::wave_tab_bytes(wm_max, wn_max, fp32);
     w.lds_bytes = int32_t(lds);
-    const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, int(lds));
+    // Prefetching A one LP ahead (measured faster for 50 x 50 in both
+    // precisions) when every LP's A fits the prefetch registers; larger or
+    // row-gathered LPs take the leaner instantiation, which runs more
+    // wavefronts per SIMD.
+    const bool pf = int64_t(wm_max) * wn_max <= lpb::wave_prefetch_elems() && !gather;
+    const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, pf, int(lds));
     if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
     const int64_t grid = std::min<int64_t>(num, int64_t(per_cu) * ctx->num_cu);
     Timer t(ctx, timing, stream, name);
-    HIP_TRY(lpb::launch_simplex_wave(fp32, rb, w, int(grid), stream));
+    HIP_TRY(lpb::launch_simplex_wave(fp32, rb, pf, w, int(grid), stream));
     t.done();
     return LP_OK;
 }
@@ -124,7 +139,7 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
     int nt = opts.block_threads;
     if (!nt) nt = cells <= 64 * 64 ? 64 : (cells <= 256 * 256 ? 256 : 512);
     int64_t lds = L.tab;
-    const bool want_lds = opts.placement != LP_PLACE_HBM && L.tab + tab_common <= ctx->max_lds;
+    const bool want_lds = opts.placement != LP_PLACE_HBM && L.tab + tab_common <= lds_budget(ctx, opts.placement);
     if (want_lds) lds = L.tab + tab_common;
     if (lds > ctx->max_lds)
         return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index "
@@ -182,7 +197,9 @@ int bin_of(int64_t m, int64_t n)
     return cells <= 64 * 64 ? 0 : cells <= 128 * 128 ? 1 : cells <= 256 * 256 ? 2 : 3;
 }
 
-int default_threads(int bin) { return bin == 0 ? 64 : bin == 1 ? 128 : bin == 2 ? 256 : 512; }
+// Untuned workgroup size: 512 threads for every bin (the autotuner picked 512 in
+// every bin of the 10..300 uneven batch on MI355X).
+int default_threads(int) { return 512; }
 
 // Estimated work of one LP: pivots grow with m + n, each pivot touches m x n cells.
 double lp_cost(int64_t m, int64_t n) { return double(m) * double(n) * double(m + n); }
@@ -191,6 +208,7 @@ struct BinLaunch {
     int m_max = 0, n_max = 0;
     int nt = 64;
     bool force_hbm = false;
+    int placement = 0;  // lp_options.placement of the call (LP_PLACE_LDS lifts the budget)
 };
 
 // One persistent launch of the workgroup kernel over the work items
@@ -206,7 +224,7 @@ int launch_block(lp_ctx *ctx, bool fp32, lpb::SolveArgs a, const BinLaunch &B, c
     const int64_t tab_common = int64_t(B.m_max + 1) * lpb::tableau_ld(B.n_max + 1) * ts;
     const int64_t tab_worst = int64_t(B.m_max + 1) * lpb::tableau_ld(ncol_worst + 1) * ts;
     int64_t lds = L.tab;
-    const bool want_lds = !B.force_hbm && L.tab + tab_common <= ctx->max_lds;
+    const bool want_lds = !B.force_hbm && L.tab + tab_common <= lds_budget(ctx, B.placement);
     if (want_lds) lds = L.tab + tab_common;
     if (lds > ctx->max_lds)
         return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index arrays "
@@ -254,6 +272,7 @@ int autotune_bin(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, BinLaunch B, i
             BinLaunch T = B;
             T.nt = nt;
             T.force_hbm = hbm != 0;
+            T.placement = hbm ? LP_PLACE_HBM : LP_PLACE_LDS;  // LDS whenever the tableau fits
             HIP_TRY(hipEventRecord(e0, stream));
             int rc = launch_block(ctx, fp32, a, T, d_sample, n_sample, nullptr, 0, nullptr, 0, q, d, stream, false, "");
             if (rc != LP_OK) return rc;
@@ -304,8 +323,10 @@ int queue_binned(lp_ctx *ctx, const Plan &P, const lpb::SolveArgs &a, const lp_o
         B.m_max = sp.m_max;
         B.n_max = sp.n_max;
         auto it = ctx->tune.find(lpb::tune_key(sp.bin, fp32));
-        B.nt = it != ctx->tune.end() ? it->second.nt : default_threads(sp.bin);
-        B.force_hbm = it != ctx->tune.end() ? it->second.force_hbm != 0 : false;
+        const bool tuned = it != ctx->tune.end();
+        B.nt = tuned ? it->second.nt : default_threads(sp.bin);
+        B.force_hbm = tuned && it->second.force_hbm != 0;
+        B.placement = tuned ? (B.force_hbm ? LP_PLACE_HBM : LP_PLACE_LDS) : opts.placement;
         if (opts.placement == LP_PLACE_HBM) B.force_hbm = true;
         int rc = launch_block(ctx, fp32, a, B, d_block + sp.offset, sp.count, nullptr, 0, nullptr, 0, pc.bq, pc.bd,
                               stream, timing, bname);
@@ -443,7 +464,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     hipStream_t stream = reinterpret_cast<hipStream_t>(opts.stream);
     DeviceGuard g(ctx->device);
 
-    // Kernel choice per LP: one wavefront for LPs of at most 63 columns and 128
+    // Kernel choice per LP: one wavefront for LPs of at most 64 columns and 128
     // rows whose tableau fits LDS, a workgroup otherwise (or when the caller
     // fixes the workgroup size or asks for HBM placement).
     const bool auto_kernel = opts.block_threads == 0 && opts.placement != LP_PLACE_HBM;
@@ -451,14 +472,14 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     int64_t n_wave = 0, rows = 0;
     int wm_max = 0, wn_max = 0;
     if (P.uniform) {
-        const bool w = auto_kernel && wave_fit(ctx, P.m0, P.n0, P.fp32);
+        const bool w = auto_kernel && wave_fit(ctx, P.m0, P.n0, P.fp32, screened);
         n_wave = w ? num_lps : 0;
         wm_max = w ? P.m0 : 0;
         wn_max = w ? P.n0 : 0;
         rows = num_lps * int64_t(P.m0);
     } else {
         for (int64_t k = 0; k < num_lps; ++k) {
-            const bool w = auto_kernel && wave_fit(ctx, m[k], n[k], P.fp32);
+            const bool w = auto_kernel && wave_fit(ctx, m[k], n[k], P.fp32, false);
             if (w) {
                 ++n_wave;
                 wm_max = std::max(wm_max, m[k]);
@@ -628,10 +649,10 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         ca.tol_opt = p64.tol_opt;
         const int kmax = std::min(P_full.m_max, P_full.n_max);
         if (kmax <= 64) {
-            // One wavefront per LP (at most 64 basic structurals); LU blocks up to
-            // kl x kl in LDS, larger ones in the wavefront's device-memory slot.
-            // Shared constraints are copied into LDS once per workgroup of W
-            // wavefronts when they fit next to W wavefront regions.
+            // One wavefront per LP; LU blocks up to kl x kl in LDS (a basis with
+            // more basic structurals, rare at these sizes, goes to the FP64
+            // re-solve).  Shared constraints are copied into LDS once per
+            // workgroup of W wavefronts when they fit next to W wavefront regions.
             const int64_t a_bytes = lpb::align16(8 * int64_t(P_full.m0) * P_full.n0);
             int W = 1, kl = std::min(kmax, 32), stage = 0;
             int64_t wb = lpb::wave_cert_layout(P_full.m_max, P_full.n_max, kl).end, lds = wb;
@@ -654,15 +675,6 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             const int per_cu = lpb::certify_wave_blocks_per_cu(W, int(lds));
             if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
             const int64_t cgrid = std::min<int64_t>((num_lps + W - 1) / W, int64_t(per_cu) * ctx->num_cu);
-            if (kmax > kl) {
-                ca.slot_bytes = 8 * 64 * 64;
-                // The LU slots share the tableau scratch (the first pass has finished
-                // with it by the time the certificate kernel runs on the same stream).
-                int rc2 = ctx->scratch.ensure(
-                    std::max<size_t>(ctx->scratch.bytes, size_t(ca.slot_bytes) * size_t(cgrid) * W));
-                if (rc2 != LP_OK) return rc2;
-                ca.scratch = static_cast<char *>(ctx->scratch.p);
-            }
             Timer t(ctx, timing, stream, "certify_fp64");
             HIP_TRY(lpb::launch_certify_wave(W, ca, int(cgrid), stream));
             t.done();
@@ -699,14 +711,14 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         int64_t n_wave64 = 0;
         int wm64 = 0, wn64 = 0;
         if (P_full.uniform) {
-            if (auto_kernel && wave_fit(ctx, P_full.m0, P_full.n0, false)) {
+            if (auto_kernel && wave_fit(ctx, P_full.m0, P_full.n0, false, false)) {
                 n_wave64 = num_lps;
                 wm64 = P_full.m0;
                 wn64 = P_full.n0;
             }
         } else {
             for (int64_t k = 0; k < num_lps && auto_kernel; ++k)
-                if (wave_fit(ctx, m[k], n[k], false)) {
+                if (wave_fit(ctx, m[k], n[k], false, false)) {
                     ++n_wave64;
                     wm64 = std::max(wm64, m[k]);
                     wn64 = std::max(wn64, n[k]);

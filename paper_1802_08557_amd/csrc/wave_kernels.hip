@@ -1,20 +1,21 @@
 // wave_kernels.hip -- one 64-wide wavefront per LP for small tableaux.
 //
-// For LPs with at most 63 non-basic columns and 64*RB rows the whole solve runs
+// For LPs with at most 64 non-basic columns and 64*RB rows the whole solve runs
 // in a single wavefront with no workgroup barrier:
 //   * lane j owns column j: its non-basic variable nonb (Bland index), its
-//     objective-row entry d_j (lane N holds minus the objective value) and, during
-//     a pivot, its pivot-row entry prow_j;
-//   * lane i (+64 r) owns row i: its basic variable, sign/sense flags and its
-//     pivot-column entry pcol_i;
-//   * the constraint rows live in LDS, column-major (lane j's column is
+//     objective-row entry d_j and, during a pivot, its pivot-row entry prow_j;
+//   * lane i (+64 r) owns row i: its basic variable, sign/sense flags, its
+//     right-hand side b_i and its pivot-column entry pcol_i; the objective
+//     row's right-hand side (minus the objective value) is a uniform value;
+//   * the constraint columns live in LDS, column-major (lane j's column is
 //     contiguous) with a column stride of an odd number of 16-byte units.
 // Step 1 is a wavefront DPP/permlane reduction over the lanes' reduced costs;
-// Step 2 reads the entering column and the rhs column (contiguous, one element
-// per lane) and reduces the ratios; Step 3 sweeps each lane's column in 16-byte
-// vectors, sixteen rows per group -- all reads, then the fma, then all writes --
-// with the rows' pivot-column entries broadcast from column e in LDS, then
-// rewrites the swapped column and the pivot row.
+// Step 2 reads the entering column (contiguous, one element per lane) and
+// reduces the ratios against the row-owned right-hand sides; Step 3 sweeps each
+// lane's column in 16-byte vectors, sixteen rows per group -- all reads, then
+// the fma, then all writes -- with the rows' pivot-column entries broadcast
+// from column e in LDS, updates the right-hand sides in the row owners'
+// registers, then rewrites the swapped column and the pivot row.
 // The arithmetic of every element (fma(-pcol_i, prow_j, t_ij), prow_j =
 // t_lj / PE, Phase I and Phase II objective rows summed in row order) is the
 // same as in the workgroup kernel, so both give bitwise-identical results.
@@ -64,11 +65,13 @@ struct WaveLP {
     int m, n, N, C, ldm, nart;
     int64_t k, ro, co;
     const double *A, *b, *c;
-    T *tab;  // column-major: element (i, j) at tab[j * ldm + i]
+    T *tab;  // column-major: element (i, j) at tab[j * ldm + i], columns 0 .. N-1
     int rowf[RB], basis[RB];
     T pcol[RB];
-    int nonb;  // this lane's column
-    T d;       // this lane's objective-row entry
+    T rhs[RB];  // right-hand side of row lane + 64 r
+    T z;        // right-hand side of the objective row (uniform)
+    int nonb;   // this lane's column
+    T d;        // this lane's objective-row entry
     int iters, it1, degp, cap;
 };
 
@@ -96,6 +99,15 @@ __device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
     if (lane < C) prow = (lane == e) ? T(1) / pe : tab[lane * ldm + l] / pe;
     const T de = lane_get(P.d, e);
     if (lane < C) P.d = fma(-de, prow, (lane == e) ? T(0) : P.d);
+    // Right-hand sides: the objective row's (uniform) and every row's, in the
+    // row owners' registers (dead and padding rows carry pcol 0 and stay).
+    const T prow_rhs = row_get<RB>(P.rhs, l) / pe;
+    P.z = fma(-de, prow_rhs, P.z);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int i = lane + 64 * r;
+        if (i < m) P.rhs[r] = (i == l) ? prow_rhs : fma(-P.pcol[r], prow_rhs, P.rhs[r]);
+    }
     // Sweep this lane's column in 16-byte vectors, G vectors (16 rows) per
     // group.  The same rows of the pivot column are read from column e by
     // every lane (one broadcast address per load); lane e rewrites column e
@@ -200,7 +212,7 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
             const int i = lane + 64 * r;
             const bool live = !(P.rowf[r] & (kRowDead | kRowPad));
             T a = T(0), bi = T(0);
-            if (i < m) { a = tab[e * ldm + i]; bi = tab[N * ldm + i]; }
+            if (i < m) { a = tab[e * ldm + i]; bi = P.rhs[r]; }
             P.pcol[r] = live ? a : T(0);
             if (live && a > tol_piv) {
                 const T th = (bi > T(0) ? bi : T(0)) / a;
@@ -227,25 +239,29 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
 }
 
 // Bytes of LDS the wave kernel keeps in front of the tableau: the surplus
-// column -> row map, the x staging vector, the LP's objective c and the
-// row -> constraint map of a screened LP.
-__host__ __device__ constexpr int64_t wave_aux_bytes(int rb, int64_t tsize)
+// column -> row map and the row -> constraint map of a screened LP.  (The
+// objective c stays in registers and is fetched across lanes with
+// ds_bpermute; x is staged in the tableau's first columns once the pivots are
+// done.)  Keeping this small lets one more 50 x 50 FP64 LP fit per CU.
+__host__ __device__ constexpr int64_t wave_aux_bytes(int rb, bool gather)
 {
-    return align16(4 * 64 * rb) + align16(tsize * 64) + 8 * 64 + 4 * 64 * rb;
+    return align16(4 * 64 * rb) + (gather ? align16(4 * 64 * rb) : 0);
 }
 
 // Doubles of A each lane prefetches: LPs with m * n <= 64 * NPF have their
-// whole constraint matrix loaded into registers one LP ahead.
+// whole constraint matrix loaded into registers one LP ahead.  Batches of
+// larger (or row-gathered) LPs use the instantiation without the prefetch
+// registers, which leaves room for more wavefronts per SIMD.
 constexpr int NPF = 40;
 
 // An LP's geometry and input data, loaded into registers ahead of its solve.
-template <int RB>
+template <int RB, int PFD>
 struct Fetch {
     int64_t k, ro, co;
     int m, n;
     const double *A;
     bool has_a;
-    double av[NPF];  // A in flat row-major order, element lane + 64 t
+    double av[PFD > 0 ? PFD : 1];  // A in flat row-major order, element lane + 64 t
     double bv[RB];   // b of row lane + 64 r
     int sv[RB];      // sense of row lane + 64 r
     int rid[RB];     // constraint of the shared LP that row lane + 64 r is (shared only)
@@ -254,8 +270,8 @@ struct Fetch {
 };
 
 // Issues the loads of work item `item` (nothing waits for them here).
-template <int RB>
-__device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB> &F)
+template <int RB, int PFD>
+__device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB, PFD> &F)
 {
     const int lane = threadIdx.x;
     const int64_t k = a.ids ? int64_t(a.ids[item]) : item;
@@ -301,37 +317,35 @@ __device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB
     }
     F.cv = (lane < n) ? a.c[F.co + lane] : 0.0;
     const int mn = m * n;
-    F.has_a = mn <= 64 * NPF && !(a.shared && a.row_subset);
-    if (F.has_a) {
+    F.has_a = PFD > 0 && mn <= 64 * PFD && !(a.shared && a.row_subset);
+    if constexpr (PFD > 0) if (F.has_a) {
         // One buffer descriptor over this LP's A: the hardware range check
         // (offset < m*n*8) returns 0 past the end instead of reading further.
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<double *>(F.A), short(0), mn * int(sizeof(double)), 0x00020000);
 #pragma unroll
-        for (int t = 0; t < NPF; ++t)
+        for (int t = 0; t < PFD; ++t)
             F.av[t] = __builtin_bit_cast(
                 double, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * t) * 8, 0, 0));
     }
 }
 
-template <typename T, int RB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void simplex_wave_kernel(SolveArgs a)
+template <typename T, int RB, int PFD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 : (sizeof(T) == 4 ? 4 : 3)))) void simplex_wave_kernel(SolveArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x;
     int *colrow = reinterpret_cast<int *>(smem);
-    T *xv = reinterpret_cast<T *>(smem + align16(4 * 64 * RB));
-    double *cl = reinterpret_cast<double *>(smem + align16(4 * 64 * RB) + align16(sizeof(T) * 64));
-    int *rowid = reinterpret_cast<int *>(smem + align16(4 * 64 * RB) + align16(sizeof(T) * 64) + 8 * 64);
-    const int64_t aux = wave_aux_bytes(RB, sizeof(T));
+    int *rowid = reinterpret_cast<int *>(smem + align16(4 * 64 * RB));
+    const int64_t aux = wave_aux_bytes(RB, a.shared && a.row_subset);
     const int64_t total = a.num_dev ? int64_t(a.id_base) + *a.num_dev : a.num;
     // Work items: blockIdx.x and blockIdx.x + G first, then 2G + the queue
     // counter; the next item is always known one LP ahead, so its data can be
     // in flight while the current LP pivots.
     const int64_t G = gridDim.x;
     int64_t cur = blockIdx.x, nxt = blockIdx.x + G;
-    Fetch<RB> F;
-    if (cur < total) fetch<RB>(a, cur, F);
+    Fetch<RB, PFD> F;
+    if (cur < total) fetch<RB, PFD>(a, cur, F);
     while (cur < total) {
         int pend = 0;
         if (lane == 0) pend = int(2 * G) + atomicAdd(a.queue, 1);
@@ -370,6 +384,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
             }
             bv[r] = bi;
             P.rowf[r] = f;
+            P.rhs[r] = (i < m) ? T((f & kRowNeg) ? -bi : bi) : T(0);
             const int sen = (f >> 1) & 3;
             const uint64_t ge = __ballot(i < m && sen == kGE);
             const uint64_t ar = __ballot(i < m && sen != kLE);
@@ -385,7 +400,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
             neq += __popcll(eq);
         }
         P.N = n + ng;
-        P.C = P.N + 1;
+        P.C = P.N;
         P.ldm = col_stride<T>(m);
         P.nart = nart;
         const int64_t need = aux + int64_t(P.C) * P.ldm * int64_t(sizeof(T));
@@ -405,7 +420,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
         if (lane < n) {
             P.nonb = lane;
             bad |= !isfinite(cj);
-            cl[lane] = cj;
         } else if (lane < N) {
             P.nonb = n + colrow[lane - n];
         }
@@ -422,9 +436,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
             const int mn = m * n;
             const int dq = 64 / n, dr = 64 - dq * n;
             int ri = lane / n, cj2 = lane - (lane / n) * n;
-            if (F.has_a) {
+            if (PFD > 0 && F.has_a) {
 #pragma unroll
-                for (int t = 0; t < NPF; ++t) {
+                for (int t = 0; t < (PFD > 0 ? PFD : 1); ++t) {
                     if (lane + 64 * t < mn) {
                         bad |= !isfinite(F.av[t]);
                         tab[cj2 * ldm + ri] = T(F.av[t]);
@@ -478,20 +492,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
                     if (lane < n) tab[lane * ldm + i] = -tab[lane * ldm + i];
                 }
             }
-            // Surplus columns and the right-hand side, one row per lane.
+            // Surplus columns, one row per lane.
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int i = lane + 64 * r;
-                if (i < m) {
-                    const double sg = (P.rowf[r] & kRowNeg) ? -1.0 : 1.0;
+                if (i < m)
                     for (int g = 0; g < ng; ++g) tab[(n + g) * ldm + i] = (sc[r] == n + g) ? T(-1) : T(0);
-                    tab[N * ldm + i] = T(sg * bv[r]);
-                }
             }
         }
         }  // fits
         // The registers of F are free again: start loading the next LP.
-        if (nxt < total) fetch<RB>(a, nxt, F);
+        if (nxt < total) fetch<RB, PFD>(a, nxt, F);
         if (!fits) {
             cur = nxt;
             nxt = lane_get(pend, 0);
@@ -506,6 +517,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
         P.iters = 0; P.it1 = 0; P.degp = 0;
         P.cap = a.prm.max_iters > 0 ? a.prm.max_iters : 50 * (m + n + (m - neq) + nart);
         P.d = T(0);
+        P.z = T(0);
         int status = kOptimal, enter = -1;
 
         if (invalid) {
@@ -513,12 +525,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
         } else {
             if (nart > 0) {
                 // Phase I objective row: sum of the artificial rows in row order.
-                T acc = T(0);
+                T acc = T(0), zacc = T(0);
                 for (int i = 0; i < m; ++i) {
                     const int sen = (row_get<RB>(P.rowf, i) >> 1) & 3;
-                    if (sen != kLE && lane < C) acc += tab[lane * ldm + i];
+                    if (sen != kLE) {
+                        if (lane < C) acc += tab[lane * ldm + i];
+                        zacc += row_get<RB>(P.rhs, i);
+                    }
                 }
                 P.d = acc;
+                P.z = zacc;
                 const double dmax = wave_max(lane < N ? fabs(double(acc)) : 0.0);
                 const double dscale = fmax(1.0, dmax);
                 const int r = simplex<T, RB>(P, T(a.prm.tol_opt * dscale), a.prm, &enter);
@@ -527,7 +543,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
                 if (r == kIterLimit) status = kIterLimit;
                 else if (r == kUnbounded) status = kNumerical;
                 else {
-                    const double wstar = -double(lane_get(P.d, N));
+                    const double wstar = -double(P.z);
                     if (wstar < -a.prm.tol_feas * (1.0 + bnorm)) status = kInfeasible;
                 }
                 if (status == kOptimal) {
@@ -560,10 +576,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     const int bvr = P.basis[r];
-                    cb[r] = (!(P.rowf[r] & (kRowDead | kRowPad)) && bvr < n) ? T(cl[bvr]) : T(0);
+                    const double cbv = __shfl(cj, bvr < n ? bvr : 0);  // c of the row's basic variable
+                    cb[r] = (!(P.rowf[r] & (kRowDead | kRowPad)) && bvr < n) ? T(cbv) : T(0);
                     nz[r] = __ballot(cb[r] != T(0));
                 }
-                T acc = (lane < N && P.nonb < n) ? T(cl[P.nonb]) : T(0);
+                const double cnb = __shfl(cj, (P.nonb >= 0 && P.nonb < n) ? P.nonb : 0);
+                T acc = (lane < N && P.nonb < n) ? T(cnb) : T(0), zacc = T(0);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     uint64_t mk = nz[r];
@@ -572,21 +590,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
                         mk &= mk - 1;
                         const T f = lane_get(cb[r], bit);
                         if (lane < C) acc = fma(-f, tab[lane * ldm + 64 * r + bit], acc);
+                        zacc = fma(-f, lane_get(P.rhs[r], bit), zacc);
                     }
                 }
                 P.d = acc;
+                P.z = zacc;
                 status = simplex<T, RB>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
             }
         }
 
         // A8: extraction through an LDS staging vector.
+        // The tableau's first columns are free now (the rhs column N is read
+        // below and lies past them): x is staged there.
+        T *xv = tab;
         if (lane < n) xv[lane] = T(0);
         if (status == kOptimal) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int i = lane + 64 * r;
                 const int bvr = P.basis[r];
-                if (i < m && bvr < n && !(P.rowf[r] & kRowDead)) xv[bvr] = tab[N * ldm + i];
+                if (i < m && bvr < n && !(P.rowf[r] & kRowDead)) xv[bvr] = P.rhs[r];
             }
         }
         const double xj = (lane < n) ? double(xv[lane]) : 0.0;
@@ -636,52 +659,66 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void si
 }
 
 
-template <typename T, int RB>
+template <typename T, int RB, int PFD>
 hipError_t launch_t(const SolveArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((simplex_wave_kernel<T, RB>), dim3(grid), dim3(64), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((simplex_wave_kernel<T, RB, PFD>), dim3(grid), dim3(64), a.lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int RB>
+template <typename T, int RB, int PFD>
 int occ_t(int lds)
 {
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &blocks, (const void *)simplex_wave_kernel<T, RB>, 64, lds) != hipSuccess)
+            &blocks, (const void *)simplex_wave_kernel<T, RB, PFD>, 64, lds) != hipSuccess)
         return 0;
     return blocks;
 }
 
+template <typename T>
+hipError_t launch_rb(int rb, bool pf, const SolveArgs &a, int grid, hipStream_t s)
+{
+    if (rb == 1) return pf ? launch_t<T, 1, NPF>(a, grid, s) : launch_t<T, 1, 0>(a, grid, s);
+    if (rb == 2) return pf ? launch_t<T, 2, NPF>(a, grid, s) : launch_t<T, 2, 0>(a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+int occ_rb(int rb, bool pf, int lds)
+{
+    if (rb == 1) return pf ? occ_t<T, 1, NPF>(lds) : occ_t<T, 1, 0>(lds);
+    if (rb == 2) return pf ? occ_t<T, 2, NPF>(lds) : occ_t<T, 2, 0>(lds);
+    return 0;
+}
+
 }  // namespace
 
-int64_t wave_lds_aux_bytes(int rb, bool fp32) { return wave_aux_bytes(rb, fp32 ? 4 : 8); }
+int64_t wave_lds_aux_bytes(int rb, bool gather) { return wave_aux_bytes(rb, gather); }
 
 int64_t wave_tab_bytes(int m, int cols, bool fp32)
 {
     return fp32 ? int64_t(cols) * col_stride<float>(m) * 4 : int64_t(cols) * col_stride<double>(m) * 8;
 }
 
-hipError_t launch_simplex_wave(bool fp32, int rb, const SolveArgs &a, int grid, hipStream_t s)
+int wave_prefetch_elems() { return 64 * NPF; }
+
+hipError_t launch_simplex_wave(bool fp32, int rb, bool pf, const SolveArgs &a, int grid, hipStream_t s)
 {
-    if (rb == 1) return fp32 ? launch_t<float, 1>(a, grid, s) : launch_t<double, 1>(a, grid, s);
-    if (rb == 2) return fp32 ? launch_t<float, 2>(a, grid, s) : launch_t<double, 2>(a, grid, s);
-    return hipErrorInvalidValue;
+    return fp32 ? launch_rb<float>(rb, pf, a, grid, s) : launch_rb<double>(rb, pf, a, grid, s);
 }
 
-int simplex_wave_blocks_per_cu(bool fp32, int rb, int lds)
+int simplex_wave_blocks_per_cu(bool fp32, int rb, bool pf, int lds)
 {
-    if (rb == 1) return fp32 ? occ_t<float, 1>(lds) : occ_t<double, 1>(lds);
-    if (rb == 2) return fp32 ? occ_t<float, 2>(lds) : occ_t<double, 2>(lds);
-    return 0;
+    return fp32 ? occ_rb<float>(rb, pf, lds) : occ_rb<double>(rb, pf, lds);
 }
 
 hipError_t simplex_wave_configure(int max_lds)
 {
-    const void *fns[] = {(const void *)simplex_wave_kernel<float, 1>,
-                         (const void *)simplex_wave_kernel<double, 1>,
-                         (const void *)simplex_wave_kernel<float, 2>,
-                         (const void *)simplex_wave_kernel<double, 2>};
+    const void *fns[] = {(const void *)simplex_wave_kernel<float, 1, NPF>, (const void *)simplex_wave_kernel<double, 1, NPF>,
+                         (const void *)simplex_wave_kernel<float, 2, NPF>, (const void *)simplex_wave_kernel<double, 2, NPF>,
+                         (const void *)simplex_wave_kernel<float, 1, 0>,   (const void *)simplex_wave_kernel<double, 1, 0>,
+                         (const void *)simplex_wave_kernel<float, 2, 0>,   (const void *)simplex_wave_kernel<double, 2, 0>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
