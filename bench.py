@@ -220,6 +220,15 @@ def warm_start_block(args):
                          resolved_fp64=int(np.sum(stats[:, 3] == 1)),
                          status_match=int(np.sum(stn[:ns] == ref.status)), compared=int(ns),
                          max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
+    if args.warm_k_sweep:
+        sweep = {}
+        for kk in [int(v) for v in args.warm_k_sweep.split(",") if v]:
+            fn = lambda out, timing=False, kk=kk: warmstart.warm_solve(
+                ctx, db, d_eval, kk, stats=True, out=out, stream=stream, time_kernels=timing)
+            out, ms, _ = timed(fn, args.warm_steps)
+            stats = out.stats.cpu().numpy()
+            sweep[str(kk)] = dict(ms_per_step=ms, resolved_fp64=int(np.sum(stats[:, 3] == 1)))
+        res["warm_fp32_cert"]["screen_size_sweep"] = sweep
     # The network's share of the warm step: inference + top-k alone.
     warmstart.screen(ctx, d_eval, K)
     torch.cuda.synchronize()
@@ -260,7 +269,8 @@ def main():
     ap.add_argument("--warm-lps", type=int, default=100_000)
     ap.add_argument("--warm-train", type=int, default=200_000)
     ap.add_argument("--warm-epochs", type=int, default=40)
-    ap.add_argument("--warm-k", type=int, default=56)
+    ap.add_argument("--warm-k", type=int, default=48, help="rows each screened LP keeps")
+    ap.add_argument("--warm-k-sweep", default="", help="also time these screen sizes, e.g. 48,52,60")
     ap.add_argument("--warm-steps", type=int, default=10)
     ap.add_argument("--warm-sample", type=int, default=20_000)
     args = ap.parse_args()

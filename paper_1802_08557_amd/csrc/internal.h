@@ -142,6 +142,11 @@ hipError_t launch_adamw(float *w, const float *g, float *m, float *v, uint16_t *
                         const MlpAdam &h, const int64_t (&decay)[6], hipStream_t s);
 hipError_t launch_cast_params(const float *w, uint16_t *w16, int64_t count, hipStream_t s);
 hipError_t launch_topk(const float *S, int64_t B, int O, int k, int32_t *out, hipStream_t s);
+// Fused inference (all layers and the top-k, tiles of 64 directions):
+// scores [B][120] and/or topk [B][k] (either may be NULL).
+hipError_t launch_mlp_infer(const float *dirs, int64_t B, const uint16_t *w16, const float *w32, float *scores,
+                            int32_t *topk, int k, hipStream_t s);
+hipError_t mlp_configure();
 
 // Closed-form box LPs (hyperbox_kernels.hip).
 hipError_t launch_hyperbox(int64_t num, int n, const double *lo, const double *hi, const double *l,

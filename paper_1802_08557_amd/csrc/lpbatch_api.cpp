@@ -378,7 +378,7 @@ int lp_ctx_create(lp_ctx **out, int device)
     }
     if (lpb::simplex_configure(ctx->max_lds) != hipSuccess ||
         lpb::simplex_wave_configure(ctx->max_lds) != hipSuccess ||
-        lpb::certify_configure(ctx->max_lds) != hipSuccess) {
+        lpb::certify_configure(ctx->max_lds) != hipSuccess || lpb::mlp_configure() != hipSuccess) {
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: could not configure kernel LDS limits");
     }

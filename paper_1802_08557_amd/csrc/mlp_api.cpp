@@ -259,14 +259,9 @@ int lp_mlp_infer(lp_ctx *ctx, int64_t B, const float *dirs, float *scores, int32
     if (!top_k && !scores) return fail(LP_ERR_ARG, "neither scores nor top_k requested");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Act L = act_layout(B, false);
-    rc = ctx->mlp.act.ensure(L.total);
-    if (rc != LP_OK) return rc;
-    rc = forward(ctx, B, dirs, L, false, s);
-    if (rc != LP_OK) return rc;
-    const float *S = ctx->mlp.act.as<float>(L.s);
-    if (scores) HIP_TRY(hipMemcpyAsync(scores, S, size_t(B) * OUT * 4, hipMemcpyDeviceToDevice, s));
-    if (top_k) HIP_TRY(lpb::launch_topk(S, B, OUT, k, top_k, s));
+    // One fused kernel: no activations leave the chip.
+    HIP_TRY(lpb::launch_mlp_infer(dirs, B, ctx->mlp.params16.as<uint16_t>(), ctx->mlp.params.as<float>(), scores,
+                                  top_k, top_k ? k : 0, s));
     return LP_OK;
 }
 

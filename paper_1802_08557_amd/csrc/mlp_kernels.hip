@@ -208,6 +208,139 @@ __global__ __launch_bounds__(64) void topk_kernel(const float *S, int64_t B, int
     }
 }
 
+
+// ---- Fused inference --------------------------------------------------------
+// All three layers and the top-k for a tile of 64 directions in one workgroup
+// of four wavefronts: the input tile and both hidden activations stay in LDS
+// (BF16), the weights stream from L2 as MFMA fragments.  The products, their
+// k order and the epilogues are those of gemm_bf16_kernel, so the scores are
+// the same bits as the layer-by-layer path.
+constexpr int kTile = 64;
+constexpr int kIn = 20, kHid = 256, kOut = 120;
+constexpr int64_t kOW1 = 0, kOB1 = kOW1 + int64_t(kHid) * kIn, kOW2 = kOB1 + kHid,
+                  kOB2 = kOW2 + int64_t(kHid) * kHid, kOW3 = kOB2 + kHid, kOB3 = kOW3 + int64_t(kOut) * kHid;
+
+// Row strides (BF16 elements) of the LDS tiles, padded so that the sixteen
+// rows one MFMA fragment load touches fall in different LDS banks.
+constexpr int kLdx = 40, kLdh = kHid + 8;
+
+__host__ __device__ constexpr int64_t infer_lds_bytes()
+{
+    return int64_t(kTile) * kLdx * 2 + 2 * int64_t(kTile) * kLdh * 2;
+}
+
+// Weight fragment: row n of a [rows][K] BF16 matrix, k = k0 .. k0+3 (zero past K or rows).
+__device__ __forceinline__ s16x4 wfrag(const uint16_t *w, int n, int rows, int K, int k0)
+{
+    s16x4 v = {0, 0, 0, 0};
+    if (n >= rows) return v;
+    if (k0 + 3 < K) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(w + int64_t(n) * K + k0);
+        v[0] = short(q.x & 0xFFFF);
+        v[1] = short(q.x >> 16);
+        v[2] = short(q.y & 0xFFFF);
+        v[3] = short(q.y >> 16);
+        return v;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (k0 + t < K) v[t] = short(w[int64_t(n) * K + k0 + t]);
+    return v;
+}
+
+// One layer on the tile: out[64][NT*16*4 waves] = act[64][K] * W^T (+ bias),
+// this wavefront taking N tiles NT*wave .. NT*wave + NT-1.  Epilogue: BF16
+// ReLU activations (h16, row stride kLdh) or FP32 scores (s32, row stride 128).
+template <int NT>
+__device__ __forceinline__ void tile_layer(const uint16_t *act, int lda, int K, const uint16_t *w, int rows,
+                                           const float *bias, uint16_t *h16, float *s32)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        s16x4 fa[4], fb[NT];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const s16x4 *>(act + (16 * a + r16) * lda + k0 + kq);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) fb[j] = wfrag(w, (NT * wave + j) * 16 + r16, rows, K, k0 + kq);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[a][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[j], acc[a][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int col = (NT * wave + j) * 16 + r16;
+            const float bj = col < rows ? bias[col] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = 16 * a + kq + t;
+                const float v = acc[a][j][t] + bj;
+                if (h16) h16[row * kLdh + col] = to_bf16(fmaxf(v, 0.f));
+                else s32[row * 128 + col] = v;
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const float *dirs, int64_t B, const uint16_t *w16,
+                                                        const float *w32, float *scores, int32_t *topk, int k)
+{
+    extern __shared__ __align__(16) char smem[];
+    uint16_t *x16 = reinterpret_cast<uint16_t *>(smem);                         // [64][kLdx]
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(smem + kTile * kLdx * 2);       // [64][kLdh]
+    uint16_t *h2 = h1 + kTile * kLdh;                                             // [64][kLdh]
+    float *sc = reinterpret_cast<float *>(h1);                                    // [64][128], after layer 2
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t b0 = int64_t(blockIdx.x) * kTile;
+    for (int e = tid; e < kTile * 32; e += 256) {
+        const int r = e >> 5, kk = e & 31;
+        const int64_t b = b0 + r;
+        x16[r * kLdx + kk] = to_bf16((b < B && kk < kIn) ? dirs[b * kIn + kk] : 0.f);
+    }
+    __syncthreads();
+    tile_layer<4>(x16, kLdx, kIn, w16 + kOW1, kHid, w32 + kOB1, h1, nullptr);
+    __syncthreads();
+    tile_layer<4>(h1, kLdh, kHid, w16 + kOW2, kHid, w32 + kOB2, h2, nullptr);
+    __syncthreads();
+    tile_layer<2>(h2, kLdh, kHid, w16 + kOW3, kOut, w32 + kOB3, nullptr, sc);
+    __syncthreads();
+    // Scores out, and the top-k of every row by rank counting (one wavefront
+    // per sixteen rows; lanes hold entries lane and lane + 64).
+    for (int rr = 0; rr < kTile / 4; ++rr) {
+        const int row = wave * (kTile / 4) + rr;
+        const int64_t b = b0 + row;
+        if (b >= B) break;
+        const float s0 = sc[row * 128 + lane];
+        const float s1 = (lane + 64 < kOut) ? sc[row * 128 + lane + 64] : 0.f;
+        if (scores) {
+            scores[b * kOut + lane] = s0;
+            if (lane + 64 < kOut) scores[b * kOut + lane + 64] = s1;
+        }
+        if (topk) {
+            // Entry t is broadcast from its owner lane's register (no LDS
+            // round trip per comparison).
+            int r0 = 0, r1 = 0;
+#pragma unroll
+            for (int t = 0; t < kOut; ++t) {
+                const float u = (t < 64) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s0), t))
+                                         : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s1), t - 64));
+                r0 += (u > s0 || (u == s0 && t < lane)) ? 1 : 0;
+                r1 += (u > s1 || (u == s1 && t < lane + 64)) ? 1 : 0;
+            }
+            if (r0 < k) topk[b * k + r0] = lane;
+            if (lane + 64 < kOut && r1 < k) topk[b * k + r1] = lane + 64;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_mlp_gemm(const MlpGemm &g, hipStream_t s)
@@ -254,6 +387,21 @@ hipError_t launch_cast_params(const float *w, uint16_t *w16, int64_t count, hipS
 {
     hipLaunchKernelGGL(cast_params_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, w, w16, count);
     return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const float *dirs, int64_t B, const uint16_t *w16, const float *w32, float *scores,
+                            int32_t *topk, int k, hipStream_t s)
+{
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((B + kTile - 1) / kTile)), dim3(256), size_t(infer_lds_bytes()), s,
+                       dirs, B, w16, w32, scores, topk, k);
+    return hipGetLastError();
+}
+
+hipError_t mlp_configure()
+{
+    return hipFuncSetAttribute((const void *)mlp_infer_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(infer_lds_bytes()));
 }
 
 hipError_t launch_topk(const float *S, int64_t B, int O, int k, int32_t *out, hipStream_t s)
