@@ -339,10 +339,16 @@ def main():
         ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True, precision=prec)
         torch.cuda.synchronize()
 
-    per_kernel = {}
+    # Per-kernel time per solve: the sum over a solve's launches (a batch of
+    # mixed sizes launches the workgroup kernel once per size bin), averaged
+    # over the timed solves.
+    timed_solves = 1 if graph is not None else args.steps
+    per_kernel, launches = {}, {}
     for nm, v in ctx.kernel_times():
-        per_kernel.setdefault(nm, []).append(v)
-    per_kernel = {nm: float(np.mean(v)) for nm, v in per_kernel.items()}
+        per_kernel[nm] = per_kernel.get(nm, 0.0) + v
+        launches[nm] = launches.get(nm, 0) + 1
+    per_kernel = {nm: float(v / timed_solves) for nm, v in per_kernel.items()}
+    launches = {nm: c // timed_solves for nm, c in launches.items()}
     dom = max(per_kernel, key=per_kernel.get)
     stats = out.stats.cpu().numpy()
     status = out.status.cpu().numpy()
@@ -361,7 +367,8 @@ def main():
         roof = dict(bound="hbm", achieved=hbm_bytes / dom_s / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                     frac=hbm_bytes / dom_s / PEAK_HBM, traffic=None)
     roof["traffic"] = measured_traffic(dom, batch.name)
-    roof.update(kernel=dom, kernel_ms=per_kernel[dom], lds_bytes_alg=lds_bytes, hbm_bytes_alg=hbm_bytes,
+    roof.update(kernel=dom, kernel_ms=per_kernel[dom], launches_per_solve=launches[dom],
+                lds_bytes_alg=lds_bytes, hbm_bytes_alg=hbm_bytes,
                 io_bytes_alg=io_bytes, lds_frac=lds_bytes / dom_s / PEAK_LDS,
                 hbm_frac=hbm_bytes / dom_s / PEAK_HBM, mean_pivots=mean_piv,
                 placement_counts={str(p): int(np.sum(stats[:, 6] == p)) for p in (1, 2, 3)})

@@ -32,6 +32,37 @@ __device__ __forceinline__ double lane_get(double v, int l)
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A register copy the compiler cannot fold back into its source, so the
+// source's register is free for a new load once the copy is made (a value
+// prefetched for the next work item can then land where the current one was).
+__device__ __forceinline__ double fresh_copy(double v)
+{
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(v >> 32)));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ P *uniform_ptr(P *p)
+{
+    return reinterpret_cast<P *>(uniform64(reinterpret_cast<int64_t>(p)));
+}
+
+// Buffer descriptor over `bytes` bytes from p (p wavefront-uniform): the
+// hardware range check makes loads at offsets >= bytes return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const void *p, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<void *>(p)), short(0), bytes, 0x00020000);
+}
+__device__ __forceinline__ double buffer_f64(__amdgpu_buffer_rsrc_t rs, int byte_off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, byte_off, 0, 0));
+}
 
 // Lexicographic argmin over the wavefront of (k1, k2) carrying p.  Keys are
 // unique (k2 is a Bland index) or all invalid, so every lane ends with the

@@ -269,30 +269,39 @@ struct Fetch {
     double cv;       // c of column lane
 };
 
-// Issues the loads of work item `item` (nothing waits for them here).
+// Issues the loads of work item `item`.  The LP's geometry is wavefront-uniform
+// (computed, or read and broadcast for batches of mixed sizes); every data
+// load is an unconditional buffer load through a uniform descriptor whose
+// range check returns 0 past the LP's end, so no branch separates the loads and
+// nothing waits for them before their first use in the next LP's setup.
 template <int RB, int PFD>
 __device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB, PFD> &F)
 {
     const int lane = threadIdx.x;
-    const int64_t k = a.ids ? int64_t(a.ids[item]) : item;
+    const int64_t k = a.ids ? int64_t(uniform(a.ids[item])) : item;
     F.k = k;
+    int m, n;
+    int64_t aoff;
     if (a.um > 0) {
-        F.m = a.um; F.n = a.un;
-        F.A = a.A + k * int64_t(a.um) * a.un;
-        F.ro = k * a.um;
-        F.co = k * a.un;
+        m = a.um; n = a.un;
+        aoff = k * int64_t(m) * n;
+        F.ro = k * m;
+        F.co = k * n;
     } else {
-        F.m = a.m[k]; F.n = a.n[k];
-        F.A = a.A + a.aoff[k];
-        F.ro = a.roff[k];
-        F.co = a.coff[k];
+        // All five loads in flight before the first broadcast waits for them.
+        const int mk = a.m[k], nk = a.n[k];
+        const int64_t ak = a.aoff[k], rk = a.roff[k], ck = a.coff[k];
+        m = uniform(mk); n = uniform(nk);
+        aoff = uniform64(ak);
+        F.ro = uniform64(rk);
+        F.co = uniform64(ck);
     }
-    const int m = F.m, n = F.n;
+    F.m = m; F.n = n;
+    F.A = a.shared ? a.A : a.A + aoff;
     F.bad_row = false;
     if (a.shared) {
         // One LP's constraints shared by the batch; a screened LP takes the
         // rows its subset names (gathered, so A is read row by row later).
-        F.A = a.A;
         const int32_t *sub = a.row_subset ? a.row_subset + k * int64_t(m) : nullptr;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -307,26 +316,23 @@ __device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB
             F.sv[r] = (i < m) ? int(a.sense[q]) : 0;
         }
     } else {
+        const __amdgpu_buffer_rsrc_t rb = buffer_over(a.b + F.ro, m * int(sizeof(double)));
+        const __amdgpu_buffer_rsrc_t rsn = buffer_over(a.sense + F.ro, m);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int i = lane + 64 * r;
             F.rid[r] = i;
-            F.bv[r] = (i < m) ? a.b[F.ro + i] : 0.0;
-            F.sv[r] = (i < m) ? int(a.sense[F.ro + i]) : 0;
+            F.bv[r] = buffer_f64(rb, i * int(sizeof(double)));
+            F.sv[r] = int(int8_t(__builtin_amdgcn_raw_buffer_load_b8(rsn, i, 0, 0)));
         }
     }
-    F.cv = (lane < n) ? a.c[F.co + lane] : 0.0;
+    F.cv = buffer_f64(buffer_over(a.c + F.co, n * int(sizeof(double))), lane * int(sizeof(double)));
     const int mn = m * n;
     F.has_a = PFD > 0 && mn <= 64 * PFD && !(a.shared && a.row_subset);
     if constexpr (PFD > 0) if (F.has_a) {
-        // One buffer descriptor over this LP's A: the hardware range check
-        // (offset < m*n*8) returns 0 past the end instead of reading further.
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<double *>(F.A), short(0), mn * int(sizeof(double)), 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs = buffer_over(F.A, mn * int(sizeof(double)));
 #pragma unroll
-        for (int t = 0; t < PFD; ++t)
-            F.av[t] = __builtin_bit_cast(
-                double, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * t) * 8, 0, 0));
+        for (int t = 0; t < PFD; ++t) F.av[t] = buffer_f64(rs, (lane + 64 * t) * int(sizeof(double)));
     }
 }
 
@@ -347,8 +353,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
     Fetch<RB, PFD> F;
     if (cur < total) fetch<RB, PFD>(a, cur, F);
     while (cur < total) {
-        int pend = 0;
-        if (lane == 0) pend = int(2 * G) + atomicAdd(a.queue, 1);
+        // The queue counter is read here and used only when this LP is done.
+        // (An increment with wrap at 2^32 - 1 is a plain +1 here; unlike an add
+        // it is not rewritten into a wavefront-combined atomic whose result is
+        // broadcast, and waited for, right away.)
+        int qv = 0;
+        if (lane == 0) qv = int(atomicInc(reinterpret_cast<unsigned *>(a.queue), 0xffffffffu));
         const int64_t k = F.k;
         WaveLP<T, RB> P;
         P.k = k;
@@ -415,7 +425,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
 
         // A2: index arrays and the tableau (column-major in LDS).
         P.nonb = kBig;
-        const double cj = F.cv;
+        const double cj = fresh_copy(F.cv);
         if (fits) {
         if (lane < n) {
             P.nonb = lane;
@@ -437,15 +447,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
             const int dq = 64 / n, dr = 64 - dq * n;
             int ri = lane / n, cj2 = lane - (lane / n) * n;
             if (PFD > 0 && F.has_a) {
+                // The element's position cj2 * ldm + ri advances by
+                // dr * ldm + dq per step, and by 1 - n * ldm more when the
+                // column wraps; only the last, partial step needs a bounds test.
+                // (Prefetched elements past m * n read as 0, so every register
+                // can be checked for finiteness.)
+                const int full = mn >> 6;
+                const int step = dr * ldm + dq, wrap = 1 - n * ldm;
+                int pos = cj2 * ldm + ri;
+#pragma unroll
+                for (int t = 0; t < (PFD > 0 ? PFD : 1); ++t) bad |= !isfinite(F.av[t]);
 #pragma unroll
                 for (int t = 0; t < (PFD > 0 ? PFD : 1); ++t) {
-                    if (lane + 64 * t < mn) {
-                        bad |= !isfinite(F.av[t]);
-                        tab[cj2 * ldm + ri] = T(F.av[t]);
-                    }
-                    ri += dq;
+                    if (t < full || (t == full && lane + 64 * t < mn)) tab[pos] = T(F.av[t]);
                     cj2 += dr;
-                    if (cj2 >= n) { cj2 -= n; ++ri; }
+                    pos += step;
+                    if (cj2 >= n) { cj2 -= n; pos += wrap; }
                 }
             } else {
                 constexpr int UB = 16;
@@ -501,19 +518,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
             }
         }
         }  // fits
-        // The registers of F are free again: start loading the next LP.
-        if (nxt < total) fetch<RB, PFD>(a, nxt, F);
-        if (!fits) {
-            cur = nxt;
-            nxt = lane_get(pend, 0);
-            continue;
-        }
-        const bool invalid = __ballot(bad) != 0;
         const double cnorm = wave_max(fabs(cj));
         double bm = 0.0;
 #pragma unroll
         for (int r = 0; r < RB; ++r) bm = fmax(bm, fabs(bv[r]));
         const double bnorm = wave_max(bm);
+        // The registers of F are free again: start loading the next LP.  (The
+        // last LP of a wavefront reloads itself, so the loads are unconditional
+        // and land in the registers the current LP's came in.)
+        fetch<RB, PFD>(a, nxt < total ? nxt : cur, F);
+        if (!fits) {
+            cur = nxt;
+            nxt = 2 * G + lane_get(qv, 0);
+            continue;
+        }
+        const bool invalid = __ballot(bad) != 0;
         P.iters = 0; P.it1 = 0; P.degp = 0;
         P.cap = a.prm.max_iters > 0 ? a.prm.max_iters : 50 * (m + n + (m - neq) + nart);
         P.d = T(0);
@@ -653,7 +672,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
             }
         }
         cur = nxt;
-        nxt = lane_get(pend, 0);
+        nxt = 2 * G + lane_get(qv, 0);
     }
     if (lane == 0) finish_launch(a.queue, a.done, a.reset_extra);
 }
