@@ -111,14 +111,17 @@ __global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t count)
 
 // dS = (sigmoid(S) - Y) / (B * O) in FP32 and BF16; row_loss[b] = sum over the
 // row of softplus(S) - Y S (summed in column order).
-__global__ void bce_kernel(const float *S, const uint8_t *Y, int64_t B, int O, float *dS, uint16_t *dS16,
-                           float *row_loss)
+__global__ __launch_bounds__(256) void bce_kernel(const float *S, const uint8_t *Y, int64_t B, int O, float *dS,
+                                                  uint16_t *dS16, float *row_loss)
 {
-    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    // One wavefront per row: lane j takes outputs j, j + 64, ...; the row's
+    // loss is reduced over the lanes by a fixed butterfly.
+    const int lane = threadIdx.x & 63;
+    const int64_t b = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (b >= B) return;
     const float inv = 1.0f / (float(B) * float(O));
     float acc = 0.f;
-    for (int j = 0; j < O; ++j) {
+    for (int j = lane; j < O; j += 64) {
         const int64_t o = b * O + j;
         const float s = S[o];
         const float y = Y[o] ? 1.f : 0.f;
@@ -129,7 +132,9 @@ __global__ void bce_kernel(const float *S, const uint8_t *Y, int64_t B, int O, f
         dS[o] = d;
         dS16[o] = to_bf16(d);
     }
-    row_loss[b] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) row_loss[b] = acc;
 }
 
 // Mean of the row losses, one workgroup, fixed order: each thread sums a
@@ -148,14 +153,25 @@ __global__ __launch_bounds__(256) void mean_kernel(const float *row_loss, int64_
     if (threadIdx.x == 0) *out = float(part[0] / (double(B) * O));
 }
 
-// db[j] = sum_b dZ[b][j], rows in order.
-__global__ void colsum_kernel(const float *dZ, int64_t B, int N, float *db)
+// db[j] = sum_b dZ[b][j]: 64 columns per workgroup; thread (c, p) sums rows
+// p, p + 16, ... of column c in order, then the sixteen partial sums are added
+// in order of p.
+__global__ __launch_bounds__(1024) void colsum_kernel(const float *dZ, int64_t B, int N, float *db)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+    __shared__ float part[16][64];
+    const int c = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s += dZ[b * N + j];
-    db[j] = s;
+    if (j < N)
+        for (int64_t b = p; b < B; b += 16) s += dZ[b * N + j];
+    part[p][c] = s;
+    __syncthreads();
+    if (p == 0 && j < N) {
+        float t = part[0][c];
+#pragma unroll
+        for (int q = 1; q < 16; ++q) t += part[q][c];
+        db[j] = t;
+    }
 }
 
 // AdamW on the FP32 master copy; decay[i] = 1 for weights, 0 for biases.
@@ -215,6 +231,99 @@ __global__ __launch_bounds__(64) void topk_kernel(const float *S, int64_t B, int
 // (BF16), the weights stream from L2 as MFMA fragments.  The products, their
 // k order and the epilogues are those of gemm_bf16_kernel, so the scores are
 // the same bits as the layer-by-layer path.
+
+// ---- Top-k by a bitonic sort over the wavefront ------------------------------
+// Key of entry t with score v: the score's bits mapped to an order-preserving
+// unsigned integer (-0 taken as +0, so equal scores give equal keys) above
+// 127 - t, so that descending key order is descending score with equal scores
+// in ascending entry order.
+__device__ __forceinline__ uint64_t topk_key(float v, int t)
+{
+    const uint32_t u = __float_as_uint(v + 0.0f);
+    const uint32_t mono = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return (uint64_t(mono) << 32) | uint32_t(127 - t);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Value of lane (lane ^ J).  DPP patterns: quad_perm [1,0,3,2] (0xB1) and
+// [2,3,0,1] (0x4E) swap at distance 1 and 2; [3,2,1,0] (0x1B) after
+// row_half_mirror (0x141, i -> i ^ 7 in each group of 8) gives i ^ 4;
+// row_half_mirror after row_mirror (0x140, i -> i ^ 15 in each row of 16) gives
+// i ^ 8; the permlane swaps exchange rows (16) and halves (32).
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+    if constexpr (J == 1) return dpp32<0xB1>(v);
+    else if constexpr (J == 2) return dpp32<0x4E>(v);
+    else if constexpr (J == 4) return dpp32<0x1B>(dpp32<0x141>(v));
+    else if constexpr (J == 8) return dpp32<0x141>(dpp32<0x140>(v));
+    else if constexpr (J == 16) {
+        auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return ((lane >> 4) & 1) ? uint32_t(p[0]) : uint32_t(p[1]);
+    } else {
+        auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane >> 5) ? uint32_t(p[0]) : uint32_t(p[1]);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v)
+{
+    return (uint64_t(xor_lane<J>(uint32_t(v >> 32))) << 32) | xor_lane<J>(uint32_t(v));
+}
+
+// One compare-exchange step (block size SZ, distance J < 64) on both halves:
+// element e keeps the larger key when bit J of e is clear exactly when bit SZ
+// of e is clear (descending blocks), the smaller otherwise.
+template <int SZ, int J>
+__device__ __forceinline__ void bitonic_step(uint64_t &k0, uint64_t &k1)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t p0 = xor_lane64<J>(k0), p1 = xor_lane64<J>(k1);
+    const bool lower = (lane & J) == 0;
+    const bool up0 = ((lane + 0) & SZ) == 0, up1 = ((lane + 64) & SZ) == 0;
+    const bool max0 = lower == up0, max1 = lower == up1;
+    // Take the partner's key when it is larger and this element keeps the
+    // larger, or it is not larger and this element keeps the smaller.
+    k0 = ((p0 > k0) == max0) ? p0 : k0;
+    k1 = ((p1 > k1) == max1) ? p1 : k1;
+}
+
+template <int SZ, int J>
+__device__ __forceinline__ void bitonic_merge2(uint64_t &a0, uint64_t &a1, uint64_t &b0, uint64_t &b1)
+{
+    if constexpr (J == 64) {
+        const uint64_t ah = a0 > a1 ? a0 : a1, al = a0 > a1 ? a1 : a0;
+        const uint64_t bh = b0 > b1 ? b0 : b1, bl = b0 > b1 ? b1 : b0;
+        a0 = ah; a1 = al; b0 = bh; b1 = bl;
+    } else {
+        bitonic_step<SZ, J>(a0, a1);
+        bitonic_step<SZ, J>(b0, b1);
+    }
+    if constexpr (J > 1) bitonic_merge2<SZ, J / 2>(a0, a1, b0, b1);
+}
+
+template <int SZ>
+__device__ __forceinline__ void bitonic_stage2(uint64_t &a0, uint64_t &a1, uint64_t &b0, uint64_t &b1)
+{
+    bitonic_merge2<SZ, SZ / 2>(a0, a1, b0, b1);
+    if constexpr (SZ < 128) bitonic_stage2<SZ * 2>(a0, a1, b0, b1);
+}
+
+// Sorts two independent sets of 128 keys, (a0, a1) and (b0, b1), each in
+// descending order over positions lane (x0) and lane + 64 (x1); all 64
+// lanes must be active.
+__device__ __forceinline__ void bitonic_desc128x2(uint64_t &a0, uint64_t &a1, uint64_t &b0, uint64_t &b1)
+{
+    bitonic_stage2<2>(a0, a1, b0, b1);
+}
+
 constexpr int kTile = 64;
 constexpr int kIn = 20, kHid = 256, kOut = 120;
 constexpr int64_t kOW1 = 0, kOB1 = kOW1 + int64_t(kHid) * kIn, kOW2 = kOB1 + kHid,
@@ -262,12 +371,20 @@ __device__ __forceinline__ void tile_layer(const uint16_t *act, int lda, int K, 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // Weight fragments are loaded one k step ahead of their use.
+    s16x4 fbn[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) fbn[j] = wfrag(w, (NT * wave + j) * 16 + r16, rows, K, kq);
     for (int k0 = 0; k0 < K; k0 += 16) {
         s16x4 fa[4], fb[NT];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const s16x4 *>(act + (16 * a + r16) * lda + k0 + kq);
+        for (int j = 0; j < NT; ++j) fb[j] = fbn[j];
+        if (k0 + 16 < K) {
 #pragma unroll
-        for (int j = 0; j < NT; ++j) fb[j] = wfrag(w, (NT * wave + j) * 16 + r16, rows, K, k0 + kq);
+            for (int j = 0; j < NT; ++j) fbn[j] = wfrag(w, (NT * wave + j) * 16 + r16, rows, K, k0 + 16 + kq);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const s16x4 *>(act + (16 * a + r16) * lda + k0 + kq);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -314,29 +431,41 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const float *dirs, int64
     __syncthreads();
     // Scores out, and the top-k of every row by rank counting (one wavefront
     // per sixteen rows; lanes hold entries lane and lane + 64).
-    for (int rr = 0; rr < kTile / 4; ++rr) {
+    // Two rows per step, so that the two sorts' independent instruction
+    // chains interleave.
+    for (int rr = 0; rr < kTile / 4; rr += 2) {
         const int row = wave * (kTile / 4) + rr;
         const int64_t b = b0 + row;
         if (b >= B) break;
-        const float s0 = sc[row * 128 + lane];
-        const float s1 = (lane + 64 < kOut) ? sc[row * 128 + lane + 64] : 0.f;
+        const bool two = b + 1 < B;
+        float s0[2], s1[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            s0[q] = sc[(row + q) * 128 + lane];
+            s1[q] = (lane + 64 < kOut) ? sc[(row + q) * 128 + lane + 64] : 0.f;
+        }
         if (scores) {
-            scores[b * kOut + lane] = s0;
-            if (lane + 64 < kOut) scores[b * kOut + lane + 64] = s1;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (q == 1 && !two) break;
+                scores[(b + q) * kOut + lane] = s0[q];
+                if (lane + 64 < kOut) scores[(b + q) * kOut + lane + 64] = s1[q];
+            }
         }
         if (topk) {
-            // Entry t is broadcast from its owner lane's register (no LDS
-            // round trip per comparison).
-            int r0 = 0, r1 = 0;
-#pragma unroll
-            for (int t = 0; t < kOut; ++t) {
-                const float u = (t < 64) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s0), t))
-                                         : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s1), t - 64));
-                r0 += (u > s0 || (u == s0 && t < lane)) ? 1 : 0;
-                r1 += (u > s1 || (u == s1 && t < lane + 64)) ? 1 : 0;
+            // Sort each row's 120 keys (and 8 padding keys below every real
+            // one) in descending order; position e = lane + 64 h then holds
+            // the entry of rank e.
+            uint64_t ka0 = topk_key(s0[0], lane), kb0 = topk_key(s0[1], lane);
+            uint64_t ka1 = (lane + 64 < kOut) ? topk_key(s1[0], lane + 64) : 0;
+            uint64_t kb1 = (lane + 64 < kOut) ? topk_key(s1[1], lane + 64) : 0;
+            bitonic_desc128x2(ka0, ka1, kb0, kb1);
+            if (lane < k) topk[b * k + lane] = 127 - int(uint32_t(ka0));
+            if (lane + 64 < k) topk[b * k + lane + 64] = 127 - int(uint32_t(ka1));
+            if (two) {
+                if (lane < k) topk[(b + 1) * k + lane] = 127 - int(uint32_t(kb0));
+                if (lane + 64 < k) topk[(b + 1) * k + lane + 64] = 127 - int(uint32_t(kb1));
             }
-            if (r0 < k) topk[b * k + r0] = lane;
-            if (lane + 64 < kOut && r1 < k) topk[b * k + r1] = lane + 64;
         }
     }
 }
@@ -361,8 +490,7 @@ hipError_t launch_to_bf16(const float *x, uint16_t *y, int64_t count, hipStream_
 hipError_t launch_bce(const float *S, const uint8_t *Y, int64_t B, int O, float *dS, uint16_t *dS16,
                       float *row_loss, float *loss, hipStream_t s)
 {
-    hipLaunchKernelGGL(bce_kernel, dim3(unsigned((B + 255) / 256)), dim3(256), 0, s, S, Y, B, O, dS, dS16,
-                       row_loss);
+    hipLaunchKernelGGL(bce_kernel, dim3(unsigned((B + 3) / 4)), dim3(256), 0, s, S, Y, B, O, dS, dS16, row_loss);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, row_loss, B, O, loss);
@@ -371,7 +499,7 @@ hipError_t launch_bce(const float *S, const uint8_t *Y, int64_t B, int O, float 
 
 hipError_t launch_colsum(const float *dZ, int64_t B, int N, float *db, hipStream_t s)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, dZ, B, N, db);
+    hipLaunchKernelGGL(colsum_kernel, dim3(unsigned((N + 63) / 64)), dim3(1024), 0, s, dZ, B, N, db);
     return hipGetLastError();
 }
 
