@@ -249,6 +249,45 @@ def warm_start_block(args):
                 final_loss=losses[-1] if losses else None, modes=res)
 
 
+def host_pipeline_block(batch, ctx, reps=3):
+    """The benchmarked batch from host memory through lp_batch_solve_host
+    (chunked upload / solve / download on three streams): end-to-end LPs/s
+    including PCIe, for pinned and pageable host buffers and for one chunk (no
+    overlap), next to the host->device copy rate of the same bytes.  Never the
+    headline value: the device-resident solve is."""
+    import torch
+    N = batch.num_lps
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+    hA, hb, hc, hs = pin(batch.A), pin(batch.b), pin(batch.c), pin(batch.sense)
+    outs = (torch.empty(N, dtype=torch.int32).pin_memory(),
+            torch.empty(int(batch.n.sum()), dtype=torch.float64).pin_memory(),
+            torch.empty(N, dtype=torch.float64).pin_memory())
+
+    def timed(fn):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return (time.perf_counter() - t0) / reps
+
+    res = {}
+    t = timed(lambda: ctx.solve_host(hA, hb, hc, hs, batch.m, batch.n, out=outs))
+    res["pinned"] = dict(ms=t * 1e3, lps_per_s=N / t)
+    t = timed(lambda: ctx.solve_host(hA, hb, hc, hs, batch.m, batch.n, out=outs, chunk_lps=N))
+    res["pinned_one_chunk"] = dict(ms=t * 1e3, lps_per_s=N / t)
+    pg = (np.empty(N, np.int32), np.empty(int(batch.n.sum())), np.empty(N))
+    t = timed(lambda: ctx.solve_host(batch.A, batch.b, batch.c, batch.sense, batch.m, batch.n, out=pg))
+    res["pageable"] = dict(ms=t * 1e3, lps_per_s=N / t)
+    st_ok = bool(np.array_equal(outs[0].numpy(), pg[0]) and np.array_equal(outs[2].numpy(), pg[2]))
+    d = torch.empty(hA.numel(), dtype=torch.float64, device="cuda")
+    t = timed(lambda: (d.copy_(hA.view(-1), non_blocking=True), torch.cuda.synchronize()))
+    in_bytes = hA.numel() * 8 + hb.numel() * 8 + hc.numel() * 8 + hs.numel()
+    res["h2d_copy_of_A"] = dict(ms=t * 1e3, gb_per_s=hA.numel() * 8 / t / 1e9)
+    res.update(input_bytes=int(in_bytes), pinned_equals_pageable=st_ok,
+               note="host buffers -> device -> host, PCIe included; not the headline value")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +312,7 @@ def main():
     ap.add_argument("--warm-k-sweep", default="", help="also time these screen sizes, e.g. 48,52,60")
     ap.add_argument("--warm-steps", type=int, default=10)
     ap.add_argument("--warm-sample", type=int, default=20_000)
+    ap.add_argument("--no-host", action="store_true", help="skip the host-resident pipeline leg")
     args = ap.parse_args()
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
@@ -394,6 +434,11 @@ def main():
         rel = np.abs(obj[:k][opt] - ref.obj[opt]) / np.maximum(1.0, np.abs(ref.obj[opt]))
         rec["parity"] = dict(compared=int(k), status_match=int(np.sum(status[:k] == ref.status)),
                              max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
+    if not args.no_host and not args.graph:
+        try:
+            rec["host_pipeline"] = host_pipeline_block(batch, ctx)
+        except Exception as e:  # the main measurement stands on its own
+            rec["host_pipeline"] = dict(error=f"{type(e).__name__}: {e}")
     if not args.no_warm and args.config == 1:
         try:
             rec["warm_start"] = warm_start_block(args)

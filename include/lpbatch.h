@@ -184,6 +184,36 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
                       const lp_options *opts);
 
 /*
+ * lp_batch_solve_host -- a batch held in HOST memory, streamed through the
+ * device in chunks (paper Sec. 5.1, Algorithm 1: the batch is cut into chunks
+ * that fit the device, each copied over, solved and copied back; and the
+ * transfer overlap of its "Data transfer and kernel execution" discussion).
+ *
+ * Same batch layout, options and results as lp_batch_solve_ex, except that
+ * A, b, c, sense, status, x and obj are HOST pointers (m and n are host arrays
+ * as always).  Chunk i's inputs go host -> device on one copy stream, its
+ * solve runs on a compute stream once they have arrived, and its status, x
+ * and obj go device -> host on a second copy stream; three chunk buffers in
+ * rotation let chunk i+1's upload and chunk i-1's download proceed while chunk
+ * i is solved.  Host buffers allocated pinned (hipHostMalloc, or a PyTorch
+ * tensor with pin_memory) are copied directly; pageable buffers are staged
+ * through pinned buffers of the context by the calling thread, which then
+ * bounds the rate.
+ *
+ * chunk_lps: LPs per chunk; 0 chooses min(Eq. (5)-style capacity of a quarter
+ * of the free device memory split over three chunk buffers,
+ * max(4096, ceil(num_lps / 8))).  opts may be NULL; opts->stats, opts->shared
+ * and opts->row_subset must be unset (LP_ERR_ARG otherwise), opts->stream and
+ * LP_FLAG_SYNC are ignored: the call is synchronous and returns when every
+ * result is in the caller's arrays.  Returns LP_OK or a negative LP_ERR_*
+ * code.
+ */
+int lp_batch_solve_host(lp_ctx *ctx, int64_t num_lps, const double *A, const double *b,
+                        const double *c, const int8_t *sense, const int32_t *m,
+                        const int32_t *n, int32_t *status, double *x, double *obj,
+                        const lp_options *opts, int64_t chunk_lps);
+
+/*
  * lp_ctx_kernel_times -- durations of every kernel launched by the context's
  * lp_batch_solve_ex calls made with LP_FLAG_TIME_KERNELS since the previous
  * lp_ctx_kernel_times call, in launch order.  Synchronises on the recorded

@@ -84,6 +84,49 @@ struct MlpState {
     DevBuf misc;               // loss scalar
 };
 
+// Grow-only pinned host buffer (hipHostMalloc).
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need)
+    {
+        if (need <= bytes) return LP_OK;
+        if (p) hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t want = std::max(need, size_t(4096));
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return fail(LP_ERR_NOMEM, "hipHostMalloc of %zu bytes failed", want);
+        }
+        bytes = want;
+        return LP_OK;
+    }
+    void release()
+    {
+        if (p) hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+// One of the rotating chunk buffers of lp_batch_solve_host: the chunk's device
+// arrays, pinned staging for pageable caller memory, and the events that order
+// upload -> solve -> download.
+struct PipeSet {
+    DevBuf dev;                 // A | b | c | sense | status | x | obj
+    PinnedBuf in, out;          // staging of inputs / outputs
+    hipEvent_t up = nullptr, solved = nullptr, down = nullptr;
+    bool pending = false;       // a download not yet collected
+    int64_t first = 0, count = 0;
+};
+
+struct HostPipe {
+    bool ready = false;
+    hipStream_t h2d = nullptr, comp = nullptr, d2h = nullptr;
+    PipeSet set[3];
+};
+
 // Tuned launch of one size bin of the workgroup kernel.
 struct TuneEntry {
     int nt;         // workgroup size
@@ -105,6 +148,7 @@ struct lp_ctx {
     size_t events_used = 0;
     lpb::MlpState mlp;
     std::map<int, lpb::TuneEntry> tune;  // size bin x precision -> launch (autotuner)
+    lpb::HostPipe pipe;                  // lp_batch_solve_host streams and buffers
 };
 
 namespace lpb {

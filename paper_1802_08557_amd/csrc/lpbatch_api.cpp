@@ -406,6 +406,16 @@ void lp_ctx_destroy(lp_ctx *ctx)
     for (lpb::DevBuf *d : {&M.params, &M.params16, &M.adam_m, &M.adam_v, &M.grads, &M.act, &M.misc})
         d->release();
     for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
+    lpb::HostPipe &H = ctx->pipe;
+    for (lpb::PipeSet &S : H.set) {
+        S.dev.release();
+        S.in.release();
+        S.out.release();
+        for (hipEvent_t e : {S.up, S.solved, S.down})
+            if (e) hipEventDestroy(e);
+    }
+    for (hipStream_t st : {H.h2d, H.comp, H.d2h})
+        if (st) hipStreamDestroy(st);
     delete ctx;
 }
 

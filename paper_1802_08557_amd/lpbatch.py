@@ -29,7 +29,7 @@ EXPORTS = ("lp_batch_solve", "lp_ctx_create", "lp_ctx_destroy", "lp_options_init
            "lp_batch_solve_ex", "lp_ctx_kernel_times", "lp_last_error",
            "lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
            "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
-           "lp_hyperbox_support", "lp_ctx_tuning")
+           "lp_hyperbox_support", "lp_ctx_tuning", "lp_batch_solve_host")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NUM_PARAMS = 20, 256, 120, 102008
 
 
@@ -89,6 +89,8 @@ def load():
     lib.lp_hyperbox_support.restype = i32
     lib.lp_ctx_tuning.argtypes = [vp, vp, i32]
     lib.lp_ctx_tuning.restype = i32
+    lib.lp_batch_solve_host.argtypes = [vp, i64] + [vp] * 9 + [ctypes.POINTER(LPOptions), i64]
+    lib.lp_batch_solve_host.restype = i32
     for nm in ("lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
                "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
            "lp_hyperbox_support", "lp_ctx_tuning"):
@@ -226,6 +228,44 @@ class Context:
             m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
             _ptr(status), _ptr(x), _ptr(obj), ctypes.byref(o)))
         return Solution(status, x, obj, st)
+
+    def solve_host(self, A, b, c, sense, m, n, *, precision=PREC_FP64, chunk_lps=0, out=None,
+                   time_kernels=False):
+        """lp_batch_solve_host on a batch in host memory: A, b, c, sense are
+        numpy arrays or CPU torch tensors (pinned tensors are copied directly,
+        pageable memory is staged by the library); m, n numpy int32.  Returns
+        (status, x, obj) as numpy arrays, or fills `out` = (status, x, obj)
+        (numpy arrays or CPU torch tensors, pinned or not)."""
+        m = np.ascontiguousarray(m, np.int32)
+        n = np.ascontiguousarray(n, np.int32)
+        N = int(m.shape[0])
+
+        def host_ptr(a, dtype, count, name):
+            if isinstance(a, np.ndarray):
+                if a.dtype != np.dtype(dtype) or not a.flags.c_contiguous or a.size < count:
+                    raise ValueError(f"{name}: need a contiguous {dtype} array of >= {count} entries")
+                return ctypes.c_void_p(a.ctypes.data)
+            import torch
+            if a.device.type != "cpu" or a.dtype != getattr(torch, dtype) or not a.is_contiguous() \
+                    or a.numel() < count:
+                raise ValueError(f"{name}: need a contiguous CPU {dtype} tensor of >= {count} entries")
+            return ctypes.c_void_p(a.data_ptr())
+
+        rows, cols, cells = int(m.sum()), int(n.sum()), int((m.astype(np.int64) * n).sum())
+        if out is None:
+            out = (np.empty(N, np.int32), np.empty(cols, np.float64), np.empty(N, np.float64))
+        status, x, obj = out
+        o = LPOptions()
+        self.lib.lp_options_init(ctypes.byref(o))
+        o.precision = precision
+        o.flags = FLAG_TIME_KERNELS if time_kernels else 0
+        _check(self.lib.lp_batch_solve_host(
+            self.handle, N, host_ptr(A, "float64", cells, "A"), host_ptr(b, "float64", rows, "b"),
+            host_ptr(c, "float64", cols, "c"), host_ptr(sense, "int8", rows, "sense"),
+            m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+            host_ptr(status, "int32", N, "status"), host_ptr(x, "float64", cols, "x"),
+            host_ptr(obj, "float64", N, "obj"), ctypes.byref(o), int(chunk_lps)))
+        return status, x, obj
 
     # Warm-start network (lp_mlp_*): tensors are torch tensors on this device.
     def _stream(self, stream):
