@@ -487,6 +487,9 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // Entries loaded ahead per group: four when sixteen wavefronts share a
+    // CU (128 VGPRs each), eight otherwise.
+    constexpr int CG = W >= 16 ? 4 : 8;
     int64_t off = 0;
     if constexpr (STAGE) {
         double *As = reinterpret_cast<double *>(smem);
@@ -606,24 +609,36 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
             // Lane t holds the t-th tight row (index and sign) and lane s the
             // s-th basic structural, so loops over T or S read them with
             // readlane instead of LDS.  M is B_TS column-major (M[s*K + t],
-            // row t in lane t); every loop over M loads eight entries ahead.
+            // row t in lane t); every loop over M loads CG entries ahead.
             const bool kfit = K <= a.kl;
             const int tl = (lane < K && kfit) ? tlist[lane] : 0;
             const int sl = (lane < K && kfit) ? slist[lane] : 0;
             const double sgt = (lane < K && kfit && (rowf[tl] & kRowNeg)) ? -1.0 : 1.0;
-            const int lk = lane < K ? lane : 0;  // an in-range row of M for idle lanes
             double rz = 0.0, cs = 0.0;
             int pos = kBig;  // step at which this lane's row became the pivot row
             int ordr = 0;    // lane p: the row chosen at step p
             if (ok) {
                 double am = 0.0;
+                // colv: this lane's entry of the column being eliminated, carried
+                // in a register from the build and then from the previous step's
+                // update; the pivot comes from its owner's register, so a step
+                // reads only the pivot row and this lane's row segment from LDS.
+                double colv = 0.0;
                 const double *At = A + int64_t(tl) * n;
-                for (int s0 = 0; s0 < K; s0 += 8) {
-                    double v[8];
+                // (LDS and A reads are issued by the K lanes that own rows only:
+                // their cost scales with the active lanes.)
+                for (int s0 = 0; s0 < K; s0 += CG) {
+                    int ci[CG];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = (s0 + q < K) ? sgt * At[lane_get(sl, s0 + q < K ? s0 + q : 0)] : 0.0;
+                    for (int q = 0; q < CG; ++q) ci[q] = lane_get(sl, s0 + q < K ? s0 + q : 0);
+                    double v[CG] = {};
+                    if (lane < K) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
+                        for (int q = 0; q < CG; ++q) v[q] = (s0 + q < K) ? sgt * At[ci[q]] : 0.0;
+                    }
+                    if (s0 == 0) colv = (lane < K) ? v[0] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < CG; ++q)
                         if (s0 + q < K && lane < K) {
                             M[(s0 + q) * K + lane] = v[q];
                             am = fmax(am, fabs(v[q]));
@@ -634,30 +649,37 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 const double amax = wave_max(am);
                 wave_sync();
                 for (int p = 0; p < K; ++p) {
-                    const double v = (lane < K && pos == kBig) ? fabs(M[p * K + lk]) : -1.0;
+                    const double v = (lane < K && pos == kBig) ? fabs(colv) : -1.0;
                     const double vmax = wave_max(v);
                     if (!(vmax > 1e-13 * fmax(1.0, amax))) { ok = false; break; }
                     const int pl = __builtin_ctzll(__ballot(v == vmax));
                     if (lane == pl) pos = p;
                     if (lane == p) ordr = pl;
                     if (lane == 0) order[p] = pl;
-                    const double uinv = 1.0 / M[p * K + pl];
+                    const double uinv = 1.0 / lane_get(colv, pl);
                     const bool act = lane < K && pos == kBig;
                     const int la = act ? lane : pl;
-                    const double l = M[p * K + la] * uinv;
+                    const double l = colv * uinv;
                     if (act) M[p * K + lane] = l;
-                    for (int j0 = p + 1; j0 < K; j0 += 8) {
-                        double pr[8], mr[8];
+                    double nextv = 0.0;
+                    if (act) {
+                        for (int j0 = p + 1; j0 < K; j0 += CG) {
+                            double pr[CG], mr[CG];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            const int j = j0 + q < K ? j0 + q : K - 1;
-                            pr[q] = M[j * K + pl];
-                            mr[q] = M[j * K + la];
+                            for (int q = 0; q < CG; ++q) {
+                                const int j = j0 + q < K ? j0 + q : K - 1;
+                                pr[q] = M[j * K + pl];
+                                mr[q] = M[j * K + la];
+                            }
+#pragma unroll
+                            for (int q = 0; q < CG; ++q) {
+                                const double u = fma(-l, pr[q], mr[q]);
+                                if (j0 + q < K) M[(j0 + q) * K + lane] = u;
+                                if (q == 0 && j0 == p + 1) nextv = u;
+                            }
                         }
-#pragma unroll
-                        for (int q = 0; q < 8; ++q)
-                            if (j0 + q < K && act) M[(j0 + q) * K + lane] = fma(-l, pr[q], mr[q]);
                     }
+                    colv = nextv;
                     wave_sync();
                 }
                 if (!ok) cert |= LP_CERT_SINGULAR_BIT;
@@ -668,16 +690,21 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 // L^T v = w, y_t = v[pos_t]) side by side, so the two chains of
                 // dependent steps overlap; lane p keeps 1 / U_pp.
                 double rinv = 0.0, wr = 0.0;
-                for (int p0 = 0; p0 < K; p0 += 8) {
-                    double mv[8], mu[8];
+                for (int p0 = 0; p0 < K; p0 += CG) {
+                    double mv[CG] = {}, mu[CG] = {};
+                    int op[CG];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int p = p0 + q < K ? p0 + q : K - 1;
-                        mv[q] = M[p * K + lk];                 // lane t: L[t][p] (rows below p)
-                        mu[q] = M[lk * K + lane_get(ordr, p)]; // lane j: U[p][j]
+                    for (int q = 0; q < CG; ++q) op[q] = lane_get(ordr, p0 + q < K ? p0 + q : K - 1);
+                    if (lane < K) {
+#pragma unroll
+                        for (int q = 0; q < CG; ++q) {
+                            const int p = p0 + q < K ? p0 + q : K - 1;
+                            mv[q] = M[p * K + lane];               // lane t: L[t][p] (rows below p)
+                            mu[q] = M[lane * K + op[q]];           // lane j: U[p][j]
+                        }
                     }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
+                    for (int q = 0; q < CG; ++q) {
                         const int p = p0 + q;
                         if (p < K) {
                             const double zp = lane_get(rz, lane_get(ordr, p));
@@ -690,16 +717,21 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                         }
                     }
                 }
-                for (int h = K - 1; h >= 0; h -= 8) {
-                    double mv[8], ml[8];
+                for (int h = K - 1; h >= 0; h -= CG) {
+                    double mv[CG] = {}, ml[CG] = {};
+                    int op[CG];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int p = h - q >= 0 ? h - q : 0;
-                        mv[q] = M[p * K + lk];                 // lane t: U[pos_t][p]
-                        ml[q] = M[lk * K + lane_get(ordr, p)]; // lane p': L[p][p']
+                    for (int q = 0; q < CG; ++q) op[q] = lane_get(ordr, h - q >= 0 ? h - q : 0);
+                    if (lane < K) {
+#pragma unroll
+                        for (int q = 0; q < CG; ++q) {
+                            const int p = h - q >= 0 ? h - q : 0;
+                            mv[q] = M[p * K + lane];               // lane t: U[pos_t][p]
+                            ml[q] = M[lane * K + op[q]];           // lane p': L[p][p']
+                        }
                     }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
+                    for (int q = 0; q < CG; ++q) {
                         const int p = h - q;
                         if (p >= 0) {
                             const int pl = lane_get(ordr, p);
@@ -725,13 +757,22 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                     const bool act = !(f & kTight);
                     const double *Ai = A + int64_t(act ? i : 0) * n;
                     double ax[4] = {0.0, 0.0, 0.0, 0.0};
-                    for (int s0 = 0; s0 < K; s0 += 8) {
-                        double av[8];
+                    for (int s0 = 0; s0 < K; s0 += CG) {
+                        int si[CG];
+                        double xq[CG];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) av[q] = Ai[lane_get(sl, s0 + q < K ? s0 + q : 0)];
+                        for (int q = 0; q < CG; ++q) {
+                            si[q] = lane_get(sl, s0 + q < K ? s0 + q : 0);
+                            xq[q] = lane_get(xr, s0 + q < K ? s0 + q : 0);
+                        }
+                        if (act) {  // only the rows that need the product read A
+                            double av[CG];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q)
-                            if (s0 + q < K) ax[q & 3] = fma(av[q], lane_get(xr, s0 + q), ax[q & 3]);
+                            for (int q = 0; q < CG; ++q) av[q] = Ai[si[q]];
+#pragma unroll
+                            for (int q = 0; q < CG; ++q)
+                                if (s0 + q < K) ax[q & 3] = fma(av[q], xq[q], ax[q & 3]);
+                        }
                     }
                     if (act) {
                         const double sg = (f & kRowNeg) ? -1.0 : 1.0;
@@ -754,14 +795,22 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                         const bool act = j < n && spos[j] < 0;
                         const int jc = act ? j : 0;
                         double ya[4] = {0.0, 0.0, 0.0, 0.0};
-                        for (int t0 = 0; t0 < K; t0 += 8) {
-                            double av[8];
+                        for (int t0 = 0; t0 < K; t0 += CG) {
+                            int ti[CG];
+                            double yq[CG];
 #pragma unroll
-                            for (int q = 0; q < 8; ++q)
-                                av[q] = A[int64_t(lane_get(tl, t0 + q < K ? t0 + q : 0)) * n + jc];
+                            for (int q = 0; q < CG; ++q) {
+                                ti[q] = lane_get(tl, t0 + q < K ? t0 + q : 0);
+                                yq[q] = lane_get(ysg, t0 + q < K ? t0 + q : 0);
+                            }
+                            if (act) {  // only non-basic columns read A
+                                double av[CG];
 #pragma unroll
-                            for (int q = 0; q < 8; ++q)
-                                if (t0 + q < K) ya[q & 3] = fma(lane_get(ysg, t0 + q), av[q], ya[q & 3]);
+                                for (int q = 0; q < CG; ++q) av[q] = A[int64_t(ti[q]) * n + jc];
+#pragma unroll
+                                for (int q = 0; q < CG; ++q)
+                                    if (t0 + q < K) ya[q & 3] = fma(yq[q], av[q], ya[q & 3]);
+                            }
                         }
                         if (act) df &= c[j] - ((ya[0] + ya[1]) + (ya[2] + ya[3])) <= tol_d;
                     }
