@@ -217,7 +217,7 @@ def warm_start_block(args):
         opt = ref.status == 0
         rel = np.abs(obj[:ns][opt] - ref.obj[opt]) / np.maximum(1.0, np.abs(ref.obj[opt]))
         res[name] = dict(lps_per_s=N / (ms * 1e-3), ms_per_step=ms, kernels_ms=kern,
-                         resolved_fp64=int(np.sum(stats[:, 3] == 1)),
+                         resolved_fp64=int(np.sum(stats[:, 3] >= 1)),
                          status_match=int(np.sum(stn[:ns] == ref.status)), compared=int(ns),
                          max_rel_obj_err=float(rel.max()) if rel.size else 0.0)
     if args.warm_k_sweep:
@@ -227,7 +227,7 @@ def warm_start_block(args):
                 ctx, db, d_eval, kk, stats=True, out=out, stream=stream, time_kernels=timing)
             out, ms, _ = timed(fn, args.warm_steps)
             stats = out.stats.cpu().numpy()
-            sweep[str(kk)] = dict(ms_per_step=ms, resolved_fp64=int(np.sum(stats[:, 3] == 1)))
+            sweep[str(kk)] = dict(ms_per_step=ms, resolved_fp64=int(np.sum(stats[:, 3] >= 1)))
         res["warm_fp32_cert"]["screen_size_sweep"] = sweep
     # The network's share of the warm step: inference + top-k alone.
     warmstart.screen(ctx, d_eval, K)
@@ -446,7 +446,7 @@ def main():
             rec["warm_start"] = dict(error=f"{type(e).__name__}: {e}")
     if args.precision == "fp32c":
         rec["certificate"] = dict(certified=int(np.sum((stats[:, 5] & 3) == 3) + np.sum((stats[:, 5] & 4) != 0)),
-                                  resolved_fp64=int(np.sum(stats[:, 3] == 1)))
+                                  resolved_fp64=int(np.sum(stats[:, 3] >= 1)))
     print(json.dumps(rec), flush=True)
     ctx.close()
     return 0

@@ -79,7 +79,8 @@ typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32_CERT64 = 1 } lp_precision;
 #define LP_STAT_PIVOTS_PHASE1 0 /* Phase I pivots                                    */
 #define LP_STAT_PIVOTS_PHASE2 1 /* Phase II pivots                                   */
 #define LP_STAT_DEGENERATE 2    /* pivots with a zero step                           */
-#define LP_STAT_FALLBACK 3      /* 1: the FP64 re-solve (or warm-start fallback) ran */
+#define LP_STAT_FALLBACK 3      /* 1: the FP64 re-solve ran from the slack basis;    
+                                   2: it ran from the screened relaxation's basis  */
 #define LP_STAT_REFINE 4        /* FP64 pivots of the fallback solve                 */
 #define LP_STAT_CERT 5          /* certificate outcome, LP_CERT_* bits              */
 #define LP_STAT_PLACEMENT 6     /* where the tableau lived, LP_PLACE_*              */
@@ -148,7 +149,11 @@ typedef struct {
      * slacks of the omitted rows, is then certified in FP64 against EVERY
      * row (primal feasibility of all m rows, reduced costs); an LP whose
      * relaxation is not optimal or whose basis fails is re-solved on all rows
-     * in FP64 from the slack basis (stats[LP_STAT_FALLBACK] = 1).  Results
+     * in FP64: first from the relaxation's final basis -- its basic
+     * structurals pivoted in, then dual simplex pivots restore feasibility on
+     * the rows it violates (stats[LP_STAT_FALLBACK] = 2); an LP this repair
+     * does not finish optimal (it needs <= rows throughout) is solved from the
+     * slack basis (stats[LP_STAT_FALLBACK] = 1).  Results
      * always refer to the full LP.  An index outside 0..m[0]-1 makes that LP
      * LP_INVALID_INPUT in the first pass and sends it to the re-solve.       */
     const int32_t *row_subset;

@@ -545,6 +545,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
         bool fallback = !(st0 == kOptimal || st0 == kUnbounded);
         if (st0 == kInvalid) fallback = a.shared && a.row_subset;
         const bool work = st0 == kOptimal || st0 == kUnbounded;
+        if (a.viol && lane == 0) a.viol[k] = kBig;  // until the primal check counts them
 
         if (work) {
             // Rows: sign normalisation and the tight set; columns: the basic set.
@@ -751,7 +752,9 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 
                 // Primal certificate: every non-tight row's slack from x_S.
                 bool pf = !(lane < K) || xr >= -tol_p;
+                int nviol = __popcll(__ballot(!pf));  // rows (and basic variables) out of bounds
                 for (int i0 = 0; i0 < m; i0 += 64) {
+                    bool rowok = true;
                     const int i = i0 + lane;
                     const int f = (i < m) ? rowf[i] : kTight;
                     const bool act = !(f & kTight);
@@ -779,13 +782,16 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                         const double r = sg * (b[i] - ((ax[0] + ax[1]) + (ax[2] + ax[3])));
                         const int sen = (f >> 1) & 3;
                         // A row left out of a screened solve can be an equality.
-                        if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;
-                        else if (sen == kLE) pf &= r >= -tol_p;
-                        else if (sen == kGE) pf &= -r >= -tol_p;
+                        if ((f & kDeadRow) || sen == kEQ) rowok = fabs(r) <= tol_p;
+                        else if (sen == kLE) rowok = r >= -tol_p;
+                        else if (sen == kGE) rowok = -r >= -tol_p;
                     }
+                    pf &= rowok;
+                    nviol += __popcll(__ballot(!rowok));
                 }
                 const bool primal_ok = wave_all(pf);
                 if (primal_ok) cert |= LP_CERT_PRIMAL_OK_BIT;
+                if (a.viol && lane == 0) a.viol[k] = nviol;
 
                 if (st0 == kOptimal && primal_ok) {
                     // Dual certificate: reduced costs of every non-basic column.

@@ -51,6 +51,18 @@ struct SolveArgs {
     int32_t lds_bytes;        // dynamic LDS of each workgroup
     int32_t force_hbm;        // 1: never keep the tableau in LDS
     int32_t refine_stats;     // 1: a re-solve -- pivots go to stats[4], stats[3] = 1
+    // Warm start of a re-solve (wavefront kernel, FP64, all-<= LPs): LP k
+    // starts from the final basis of a relaxation solved on warm_m of its rows
+    // -- warm_basis[k*warm_m + r] is the Bland index (relaxation numbering) of
+    // the variable basic in relaxation row r, which is row warm_rows[k*warm_m + r]
+    // of the LP.  Structurals are pivoted in, then the dual simplex method
+    // repairs primal feasibility; an LP the repair does not finish optimal is
+    // deferred to the workgroup kernel, which solves it from the slack basis.
+    const int32_t *warm_basis;
+    const int32_t *warm_rows;
+    int32_t warm_m;
+    const int32_t *warm_viol; // optional [num]: rows the relaxation's optimum violates; more
+    int32_t warm_max_viol;    //   than warm_max_viol sends the LP to the slack-basis solve
     SolveParams prm;
 };
 
@@ -72,6 +84,7 @@ struct CertArgs {
     const int32_t *enter;     // entering variable at UNBOUNDED
     int32_t *fb_ids;          // LPs to re-solve in FP64 are appended here
     int32_t *fb_count;
+    int32_t *viol;            // optional [num]: rows the basis's x violates (wavefront kernel)
     char *scratch;            // LU matrices too large for LDS, one slot per workgroup
     int64_t slot_bytes;
     int32_t *queue, *done;
@@ -171,6 +184,9 @@ hipError_t simplex_configure(int max_lds);
 // pf: the instantiation that prefetches each next LP's A into registers
 // (LPs of at most wave_prefetch_elems() entries, A not row-gathered).
 hipError_t launch_simplex_wave(bool fp32, int rb, bool pf, const SolveArgs &a, int grid, hipStream_t s);
+// The warm-start (repair) instantiation: FP64, no prefetch; a.warm_basis set.
+hipError_t launch_simplex_wave_warm(int rb, const SolveArgs &a, int grid, hipStream_t s);
+int simplex_wave_warm_blocks_per_cu(int rb, int lds_bytes);
 int simplex_wave_blocks_per_cu(bool fp32, int rb, bool pf, int lds_bytes);
 int wave_prefetch_elems();
 int64_t wave_lds_aux_bytes(int rb, bool gather);

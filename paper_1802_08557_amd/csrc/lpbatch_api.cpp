@@ -106,12 +106,15 @@ int launch_wave(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, PassCounters pc
     // precisions) when every LP's A fits the prefetch registers; larger or
     // row-gathered LPs take the leaner instantiation, which runs more
     // wavefronts per SIMD.
-    const bool pf = int64_t(wm_max) * wn_max <= lpb::wave_prefetch_elems() && !gather;
-    const int per_cu = lpb::simplex_wave_blocks_per_cu(fp32, rb, pf, int(lds));
+    const bool warm = a.warm_basis != nullptr && !fp32;
+    const bool pf = int64_t(wm_max) * wn_max <= lpb::wave_prefetch_elems() && !gather && !warm;
+    const int per_cu = warm ? lpb::simplex_wave_warm_blocks_per_cu(rb, int(lds))
+                            : lpb::simplex_wave_blocks_per_cu(fp32, rb, pf, int(lds));
     if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the wavefront kernel");
     const int64_t grid = std::min<int64_t>(num, int64_t(per_cu) * ctx->num_cu);
     Timer t(ctx, timing, stream, name);
-    HIP_TRY(lpb::launch_simplex_wave(fp32, rb, pf, w, int(grid), stream));
+    if (warm) HIP_TRY(lpb::launch_simplex_wave_warm(rb, w, int(grid), stream));
+    else HIP_TRY(lpb::launch_simplex_wave(fp32, rb, pf, w, int(grid), stream));
     t.done();
     return LP_OK;
 }
@@ -517,7 +520,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     // entering variables [num_lps].
     const size_t sz_shape = P.uniform ? 0 : size_t(num_lps) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
     const size_t sz_ids = size_t(num_lps) * sizeof(int32_t);
-    const size_t sz_fp32 = certify ? lpb::align16(size_t(rows) * 4) + lpb::align16(sz_ids) : 0;
+    const size_t sz_fp32 = certify ? lpb::align16(size_t(rows) * 4) + 2 * lpb::align16(sz_ids) : 0;
     {
         int rc = ctx->meta.ensure(sz_shape + 4 * lpb::align16(sz_ids) + sz_fp32);
         if (rc != LP_OK) return rc;
@@ -529,6 +532,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     int32_t *d_fb_defer = reinterpret_cast<int32_t *>(meta + sz_shape + 3 * lpb::align16(sz_ids));
     int32_t *d_basis = reinterpret_cast<int32_t *>(meta + sz_shape + 4 * lpb::align16(sz_ids));
     int32_t *d_enter = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(d_basis) + lpb::align16(size_t(rows) * 4));
+    int32_t *d_viol = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(d_enter) + lpb::align16(sz_ids));
     // Uneven batches with automatic kernel choice: size bins for the LPs the
     // wavefront kernel cannot take, each bin ordered by estimated work
     // (largest first), bins largest first; plus a sample of every bin for the
@@ -653,6 +657,8 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         ca.status = status; ca.x = x; ca.obj = obj; ca.stats = opts.stats;
         ca.basis = d_basis; ca.enter = d_enter;
         ca.fb_ids = d_fb_ids; ca.fb_count = fb_count;
+        ca.viol = nullptr;
+        bool viol_counted = false;
         ca.queue = cert_q; ca.done = cert_d;
         const lpb::SolveParams p64 = fill_params(opts, false);
         ca.tol_feas = p64.tol_feas;
@@ -682,6 +688,10 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             ca.kl = kl;
             ca.stage_a = stage;
             ca.lds_bytes = int32_t(lds);
+            if (screened) {
+                ca.viol = d_viol;
+                viol_counted = true;
+            }
             const int per_cu = lpb::certify_wave_blocks_per_cu(W, int(lds));
             if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
             const int64_t cgrid = std::min<int64_t>((num_lps + W - 1) / W, int64_t(per_cu) * ctx->num_cu);
@@ -717,6 +727,18 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         a64.enter_out = nullptr;
         a64.refine_stats = 1;
         a64.row_subset = nullptr;
+        if (screened) {
+            // Start each re-solve from its relaxation's final basis and repair it
+            // with the dual simplex method (LPs it does not finish go on to a
+            // solve from the slack basis).
+            a64.warm_basis = d_basis;
+            a64.warm_rows = opts.row_subset;
+            a64.warm_m = opts.subset_m;
+            // A relaxation optimum that violates many rows is far from the
+            // LP's: the slack-basis solve is cheaper than the repair then.
+            a64.warm_viol = viol_counted ? d_viol : nullptr;
+            a64.warm_max_viol = 16;
+        }
         if (P_full.uniform) a64.um = P_full.m0;
         int64_t n_wave64 = 0;
         int wm64 = 0, wn64 = 0;

@@ -238,6 +238,151 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
     }
 }
 
+// Warm start from the final basis of a relaxation solved on a subset of the
+// rows (all rows <= after normalisation, so the tableau starts at the slack
+// basis).  The relaxation's basis holds its basic structurals and the slacks
+// of some of its rows; the other relaxation rows ("tight": slack non-basic)
+// must lose their slacks.  Crash: every basic structural enters, in
+// relaxation row order, at the tight row of largest |entry| in its column not
+// yet used; the full LP's basis then is the relaxation's plus the slacks of
+// the omitted rows.  Returns false when a pivot entry falls below tol_piv or
+// the relaxation basis is not square on its tight rows.
+template <typename T, int RB>
+__device__ bool crash(WaveLP<T, RB> &P, const SolveArgs &a, int64_t k)
+{
+    const int lane = threadIdx.x;
+    const int wm = a.warm_m, n = P.n, m = P.m, ldm = P.ldm;
+    const int32_t *wb = a.warm_basis + k * int64_t(wm);
+    const int32_t *wr = a.warm_rows + k * int64_t(wm);
+    const T tol_piv = T(a.prm.tol_piv);
+    uint64_t cand[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) cand[r] = 0;
+    int nstruct = 0;
+    // Tight rows: the relaxation's rows, less those whose slack is basic.
+    for (int r0 = 0; r0 < wm; r0 += 64) {
+        const int r = r0 + lane;
+        int q = -1, v = -1, qs = -1;
+        if (r < wm) {
+            q = wr[r];
+            v = wb[r];
+            if (v >= n && v < n + wm) qs = wr[v - n];  // the row of a basic slack
+        }
+        nstruct += __popcll(__ballot(r < wm && v >= 0 && v < n));
+        for (int pass = 0; pass < 2; ++pass) {
+            const int qq = pass == 0 ? q : qs;
+            uint64_t bits = __ballot(qq >= 0 && qq < m);
+            while (bits) {
+                const int src = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                const int qi = lane_get(qq, src);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    if ((qi >> 6) == rb) {
+                        if (pass == 0) cand[rb] |= uint64_t(1) << (qi & 63);
+                        else cand[rb] &= ~(uint64_t(1) << (qi & 63));
+                    }
+            }
+        }
+    }
+    int ntight = 0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) ntight += __popcll(cand[r]);
+    if (ntight != nstruct) return false;
+    for (int r0 = 0; r0 < wm; r0 += 64) {
+        const int r = r0 + lane;
+        const int v = r < wm ? wb[r] : -1;
+        uint64_t bits = __ballot(r < wm && v >= 0 && v < n);
+        while (bits) {
+            const int src = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const int j = lane_get(v, src);
+            const uint64_t at = __ballot(P.nonb == j);
+            if (!at) return false;  // listed twice
+            const int c = __builtin_ctzll(at);
+            T best = T(-1);
+            int rl = -1;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int i = lane + 64 * rb;
+                if (i < m && ((cand[rb] >> lane) & 1)) {
+                    const T t = fabs(P.tab[c * ldm + i]);
+                    if (t > best) { best = t; rl = i; }
+                }
+            }
+            const T bmax = wave_max_f(best);
+            if (!(bmax > tol_piv)) return false;
+            const int l = lane_get(rl, __builtin_ctzll(__ballot(rl >= 0 && best == bmax)));
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                if ((l >> 6) == rb) cand[rb] &= ~(uint64_t(1) << (l & 63));
+            load_pcol<T, RB>(P, c);
+            pivot<T, RB>(P, l, c);
+            ++P.iters;
+        }
+    }
+    return true;
+}
+
+// Repair of a start basis that is dual feasible up to the single-precision
+// level (the final basis of an FP32 relaxation) but may violate rows: the
+// dual simplex method, with d_j taken as min(d_j, 0), restores primal
+// feasibility -- the leaving row is the most negative right-hand side below
+// -tol_p (ties to the smallest basic Bland index), the entering column the
+// smallest min(d_j, 0) / t_lj over t_lj < -tol_piv (ties to the smallest Bland
+// index) -- and the primal method then removes any d_j > eps_opt left.
+// Returns the status, or -1 when the start is further from dual feasibility
+// than tol_dual (the caller then solves from the slack basis).
+template <typename T, int RB>
+__device__ int dual_repair(WaveLP<T, RB> &P, T eps_opt, T tol_dual, T tol_p, const SolveParams &prm, int *enter)
+{
+    const int lane = threadIdx.x;
+    const int m = P.m, N = P.N, ldm = P.ldm, nm = P.n + P.m;
+    const T tol_piv = T(prm.tol_piv);
+    if (__ballot(lane < N && P.d > tol_dual && P.nonb < nm)) return -1;
+    for (;;) {
+        if (P.iters >= P.cap) return kIterLimit;
+        T vl = t_inf<T>();
+        int bl = kBig, rl = -1;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = lane + 64 * r;
+            const T v = P.rhs[r];
+            if (i < m && !(P.rowf[r] & (kRowDead | kRowPad)) && v < -tol_p &&
+                (v < vl || (v == vl && P.basis[r] < bl))) {
+                vl = v; bl = P.basis[r]; rl = i;
+            }
+        }
+        if (!__ballot(rl >= 0)) break;  // primal feasible
+        const T vmin = wave_min_f(vl);
+        const uint64_t tied = __ballot(rl >= 0 && vl == vmin);
+        int src = __builtin_ctzll(tied);
+        if (__popcll(tied) > 1) {
+            const bool in = (tied >> lane) & 1;
+            const int bmin = wave_min_i(in ? bl : kBig);
+            src = __builtin_ctzll(__ballot(in && bl == bmin));
+        }
+        const int l = lane_get(rl, src);
+        T tlj = T(0);
+        if (lane < N) tlj = P.tab[lane * ldm + l];
+        const bool el = lane < N && P.nonb < nm && tlj < -tol_piv;
+        if (!__ballot(el)) return kInfeasible;  // row l cannot reach its bound
+        const T ratio = el ? (P.d < T(0) ? P.d : T(0)) / tlj : t_inf<T>();
+        const T rmin = wave_min_f(ratio);
+        const uint64_t rt = __ballot(el && ratio == rmin);
+        int e = __builtin_ctzll(rt);
+        if (__popcll(rt) > 1) {
+            const bool in = (rt >> lane) & 1;
+            const int bmin = wave_min_i(in ? P.nonb : kBig);
+            e = __builtin_ctzll(__ballot(in && P.nonb == bmin));
+        }
+        load_pcol<T, RB>(P, e);
+        pivot<T, RB>(P, l, e);
+        ++P.iters;
+    }
+    return simplex<T, RB>(P, eps_opt, prm, enter);
+}
+
 // Bytes of LDS the wave kernel keeps in front of the tableau: the surplus
 // column -> row map and the row -> constraint map of a screened LP.  (The
 // objective c stays in registers and is fetched across lanes with
@@ -336,7 +481,7 @@ __device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB
     }
 }
 
-template <typename T, int RB, int PFD>
+template <typename T, int RB, int PFD, bool WARM = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 : (sizeof(T) == 4 ? 4 : 3)))) void simplex_wave_kernel(SolveArgs a)
 {
     extern __shared__ __align__(16) char smem[];
@@ -539,10 +684,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
         P.z = T(0);
         int status = kOptimal, enter = -1;
 
+        // Warm start (repair instantiation): only from a relaxation that ended
+        // optimal (its status is still in status[k]) with few violated rows,
+        // and only for all-<= LPs; any other LP is solved from the slack basis
+        // right here.  An LP whose repair fails is deferred.
+        bool warm_ok = false, warm_defer = false;
         if (invalid) {
             status = kInvalid;
         } else {
-            if (nart > 0) {
+            if constexpr (WARM) {
+                warm_ok = nart == 0 && a.status[k] == kOptimal &&
+                          !(a.warm_viol && a.warm_viol[k] > a.warm_max_viol);
+                if (warm_ok) warm_defer = !crash<T, RB>(P, a, k);
+            }
+            if (warm_defer) {
+                // nothing more here: the LP goes to the solve from the slack basis
+            } else if (nart > 0) {
                 // Phase I objective row: sum of the artificial rows in row order.
                 T acc = T(0), zacc = T(0);
                 for (int i = 0; i < m; ++i) {
@@ -588,7 +745,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
                     }
                 }
             }
-            if (status == kOptimal) {
+            if (status == kOptimal && !warm_defer) {
                 // Phase II objective row: c priced out over the basis, rows in order.
                 T cb[RB];
                 uint64_t nz[RB];
@@ -614,8 +771,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
                 }
                 P.d = acc;
                 P.z = zacc;
-                status = simplex<T, RB>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
+                if (WARM && warm_ok) {
+                    // Single-precision level for the start's reduced costs.
+                    status = dual_repair<T, RB>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), T(1e-5 * fmax(1.0, cnorm)),
+                                                T(a.prm.tol_feas * (1.0 + bnorm)), a.prm, &enter);
+                    warm_defer = status != kOptimal;
+                } else {
+                    status = simplex<T, RB>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
+                }
             }
+        }
+        if (WARM && warm_defer) {
+            if (lane == 0) {
+                const int slot = a.defer_base + atomicAdd(a.defer_count, 1);
+                a.defer_ids[slot] = int32_t(k);
+            }
+            cur = nxt;
+            nxt = 2 * G + lane_get(qv, 0);
+            continue;
         }
 
         // A8: extraction through an LDS staging vector.
@@ -650,7 +823,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
             if (a.stats) {
                 int32_t *st = a.stats + 8 * k;
                 if (a.refine_stats) {
-                    st[3] = 1;
+                    st[3] = warm_ok ? 2 : 1;  // 2: started from the relaxation's basis
                     st[4] = P.iters;
                 } else {
                     st[0] = P.it1;
@@ -678,19 +851,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
 }
 
 
-template <typename T, int RB, int PFD>
+template <typename T, int RB, int PFD, bool WARM = false>
 hipError_t launch_t(const SolveArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((simplex_wave_kernel<T, RB, PFD>), dim3(grid), dim3(64), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((simplex_wave_kernel<T, RB, PFD, WARM>), dim3(grid), dim3(64), a.lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int RB, int PFD>
+template <typename T, int RB, int PFD, bool WARM = false>
 int occ_t(int lds)
 {
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &blocks, (const void *)simplex_wave_kernel<T, RB, PFD>, 64, lds) != hipSuccess)
+            &blocks, (const void *)simplex_wave_kernel<T, RB, PFD, WARM>, 64, lds) != hipSuccess)
         return 0;
     return blocks;
 }
@@ -732,12 +905,29 @@ int simplex_wave_blocks_per_cu(bool fp32, int rb, bool pf, int lds)
     return fp32 ? occ_rb<float>(rb, pf, lds) : occ_rb<double>(rb, pf, lds);
 }
 
+hipError_t launch_simplex_wave_warm(int rb, const SolveArgs &a, int grid, hipStream_t s)
+{
+    if (!a.warm_basis || !a.warm_rows || a.warm_m < 1) return hipErrorInvalidValue;
+    if (rb == 1) return launch_t<double, 1, 0, true>(a, grid, s);
+    if (rb == 2) return launch_t<double, 2, 0, true>(a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+int simplex_wave_warm_blocks_per_cu(int rb, int lds)
+{
+    if (rb == 1) return occ_t<double, 1, 0, true>(lds);
+    if (rb == 2) return occ_t<double, 2, 0, true>(lds);
+    return 0;
+}
+
 hipError_t simplex_wave_configure(int max_lds)
 {
     const void *fns[] = {(const void *)simplex_wave_kernel<float, 1, NPF>, (const void *)simplex_wave_kernel<double, 1, NPF>,
                          (const void *)simplex_wave_kernel<float, 2, NPF>, (const void *)simplex_wave_kernel<double, 2, NPF>,
                          (const void *)simplex_wave_kernel<float, 1, 0>,   (const void *)simplex_wave_kernel<double, 1, 0>,
-                         (const void *)simplex_wave_kernel<float, 2, 0>,   (const void *)simplex_wave_kernel<double, 2, 0>};
+                         (const void *)simplex_wave_kernel<float, 2, 0>,   (const void *)simplex_wave_kernel<double, 2, 0>,
+                         (const void *)simplex_wave_kernel<double, 1, 0, true>,
+                         (const void *)simplex_wave_kernel<double, 2, 0, true>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;

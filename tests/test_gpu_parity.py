@@ -215,7 +215,7 @@ def test_fp32_certified_two_phase_and_uneven(ctx):
     bt = W.uneven_batch(200, seed=1002)
     st, obj, x, stats, ref = check_fp32(ctx, bt)
     assert np.any((stats[:, 5] & 4) != 0)   # unbounded rays certified in FP64
-    assert np.any(stats[:, 3] == 1)          # infeasible LPs went to the FP64 re-solve
+    assert np.any(stats[:, 3] >= 1)          # infeasible LPs went to the FP64 re-solve
 
 
 def test_fp32_certified_support_and_large(ctx):

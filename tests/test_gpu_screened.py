@@ -170,3 +170,31 @@ def test_shared_argument_errors(env):
     db.m[3] = 119
     with pytest.raises(lpbatch.LPBatchError):  # shared needs equal sizes
         ctx.solve(db)
+
+
+def test_screened_repair_from_relaxation_basis(env):
+    # Subsets that hold every tight row but one: the relaxation's optimum
+    # violates the missing row, the certificate rejects it, and the FP64
+    # re-solve starts from the relaxation's basis (its structurals pivoted in,
+    # then dual simplex pivots) instead of the slack basis, and still matches
+    # the oracle.  The box rows (80..119) keep every relaxation bounded.
+    A1, b1, s1, c, bt = _support(1500, 505)
+    ref = oracle_solve(bt)
+    tight = mlp.tight_mask(A1, b1, ref.x.reshape(-1, 40))
+    rng = np.random.default_rng(6)
+    K = 64
+    sub = np.empty((bt.num_lps, K), np.int32)
+    for k in range(bt.num_lps):
+        tk = np.where(tight[k])[0]
+        t = rng.permutation(tk)[1:]  # drop one tight row
+        box = np.setdiff1d(np.arange(80, 120), tk)
+        rest = rng.permutation(np.setdiff1d(np.arange(80), tk))[:K - t.size - box.size]
+        sub[k] = rng.permutation(np.concatenate([t, box, rest]))
+    st, obj, x, stats = _solve(env, A1, b1, s1, c, sub, precision=1)
+    assert_parity(bt, st, obj, x, ref)
+    fb = stats[:, 3] >= 1
+    assert fb.sum() > 100, fb.sum()
+    # Most are repaired from the relaxation's basis rather than re-solved from
+    # the slack basis (a relaxation optimum that violates more than 16 rows
+    # goes to the slack-basis solve).
+    assert np.mean(stats[fb, 3] == 2) > 0.3, np.bincount(stats[fb, 3])
