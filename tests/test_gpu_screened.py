@@ -198,3 +198,43 @@ def test_screened_repair_from_relaxation_basis(env):
     # the slack basis (a relaxation optimum that violates more than 16 rows
     # goes to the slack-basis solve).
     assert np.mean(stats[fb, 3] == 2) > 0.3, np.bincount(stats[fb, 3])
+
+
+def test_full_size_support_batch_warm_and_plain(env):
+    # The benchmarked configuration at its full size (1e5 directions over the
+    # 120 x 40 polytope), in the launch configuration bench.py times: plain
+    # FP64, FP32 + certificate, and the network-screened solve (network
+    # trained briefly here); a sample of 4,000 LPs is checked against the
+    # oracle one by one, and every LP's status must agree across the modes.
+    torch, lpbatch, ctx = env
+    from paper_1802_08557_amd import warmstart
+    P = W.polytope(1003)
+    A1, b1 = W.split_form(P)
+    s1 = np.zeros(A1.shape[0], np.int8)
+    dirs = W.directions(100_000, 1103)
+    c = np.concatenate([dirs, -dirs], axis=1)
+    db = lpbatch.DeviceBatch.shared_from_host(A1, b1, s1, c)
+    tr = W.directions(40_000, 1203)
+    bt_tr = W.support_batch(P, tr)
+    r_tr = oracle.solve(bt_tr.A, bt_tr.b, bt_tr.c, bt_tr.sense, bt_tr.m, bt_tr.n, threads=8)
+    Y = mlp.tight_mask(A1, b1, r_tr.x.reshape(-1, 40))
+    net = lpbatch.Context(0)
+    net.mlp_init(7)
+    print("[gpu] train 8 epochs on 40k directions", flush=True)
+    warmstart.train(net, torch.from_numpy(tr.astype(np.float32)).cuda(), torch.from_numpy(Y).cuda(),
+                    epochs=8, seed=11)
+    top = warmstart.screen(net, torch.from_numpy(dirs.astype(np.float32)).cuda(), 48)
+    results = {}
+    for name, kw in [("plain", {}), ("fp32c", dict(precision=1)), ("warm", dict(precision=1, row_subset=top))]:
+        print(f"[gpu] full-size support batch: {name}", flush=True)
+        sol = ctx.solve(db, stats=True, **kw)
+        torch.cuda.synchronize()
+        results[name] = (sol.status.cpu().numpy(), sol.obj.cpu().numpy(), sol.x.cpu().numpy())
+    net.close()
+    idx = np.random.default_rng(7).choice(100_000, 4000, replace=False)
+    sample = W.support_batch(P, dirs[idx])
+    ref = oracle_solve(sample)
+    for name, (st, obj, x) in results.items():
+        xs = x.reshape(-1, 40)[idx].reshape(-1)
+        assert_parity(sample, st[idx], obj[idx], xs, ref)
+        np.testing.assert_array_equal(st, results["plain"][0])
