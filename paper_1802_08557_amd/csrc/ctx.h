@@ -46,8 +46,8 @@ struct DevBuf {
         if (need <= bytes) return LP_OK;
         // Work queued earlier may still use the old buffer: let it finish first.
         if (p) {
-            hipDeviceSynchronize();
-            hipFree(p);
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
         }
         p = nullptr;
         bytes = 0;
@@ -61,7 +61,7 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -91,7 +91,7 @@ struct PinnedBuf {
     int ensure(size_t need)
     {
         if (need <= bytes) return LP_OK;
-        if (p) hipHostFree(p);
+        if (p) (void)hipHostFree(p);
         p = nullptr;
         bytes = 0;
         size_t want = std::max(need, size_t(4096));
@@ -104,7 +104,7 @@ struct PinnedBuf {
     }
     void release()
     {
-        if (p) hipHostFree(p);
+        if (p) (void)hipHostFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -157,14 +157,14 @@ struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
     {
-        hipGetDevice(&prev);
-        if (prev != dev) hipSetDevice(dev);
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
     }
     ~DeviceGuard()
     {
         int cur = -1;
-        hipGetDevice(&cur);
-        if (prev >= 0 && cur != prev) hipSetDevice(prev);
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
     }
 };
 
@@ -191,12 +191,12 @@ struct Timer {
         kt.start = take_event(ctx);
         kt.stop = take_event(ctx);
         if (!kt.start || !kt.stop) { on = false; return; }
-        hipEventRecord(kt.start, s);
+        (void)hipEventRecord(kt.start, s);
     }
     void done()
     {
         if (!on) return;
-        hipEventRecord(kt.stop, s);
+        (void)hipEventRecord(kt.stop, s);
         ctx->times.push_back(kt);
         on = false;
     }

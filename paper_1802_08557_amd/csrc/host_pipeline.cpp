@@ -210,7 +210,7 @@ extern "C" int lp_batch_solve_host(lp_ctx *ctx, int64_t num_lps, const double *A
     // On a failure: let the queued copies and solves finish (they use the
     // context's buffers), forget the pending downloads, return the error.
     auto bail = [&](int r) {
-        for (hipStream_t st : {H.h2d, H.comp, H.d2h}) hipStreamSynchronize(st);
+        for (hipStream_t st : {H.h2d, H.comp, H.d2h}) (void)hipStreamSynchronize(st);
         for (lpb::PipeSet &S : H.set) S.pending = false;
         return r;
     };

@@ -401,24 +401,24 @@ void lp_ctx_destroy(lp_ctx *ctx)
 {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     ctx->scratch.release();
     ctx->meta.release();
     ctx->counters.release();
     lpb::MlpState &M = ctx->mlp;
     for (lpb::DevBuf *d : {&M.params, &M.params16, &M.adam_m, &M.adam_v, &M.grads, &M.act, &M.misc})
         d->release();
-    for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     lpb::HostPipe &H = ctx->pipe;
     for (lpb::PipeSet &S : H.set) {
         S.dev.release();
         S.in.release();
         S.out.release();
         for (hipEvent_t e : {S.up, S.solved, S.down})
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     }
     for (hipStream_t st : {H.h2d, H.comp, H.d2h})
-        if (st) hipStreamDestroy(st);
+        if (st) (void)hipStreamDestroy(st);
     delete ctx;
 }
 

@@ -34,8 +34,6 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
     return uint16_t(u >> 16);
 }
 
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
-
 // Four consecutive-k operand values of row (or column) r, k = k0 .. k0 + 3;
 // zero outside [0, R) x [0, K).
 __device__ __forceinline__ s16x4 load_frag(const uint16_t *p, int r, int R, int64_t sr, int k0, int K,
