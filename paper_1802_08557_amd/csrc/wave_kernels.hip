@@ -482,7 +482,7 @@ __device__ __forceinline__ void fetch(const SolveArgs &a, int64_t item, Fetch<RB
 }
 
 template <typename T, int RB, int PFD, bool WARM = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 : (sizeof(T) == 4 ? 4 : 3)))) void simplex_wave_kernel(SolveArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 : (sizeof(T) == 4 ? (RB == 1 ? 5 : 4) : 3)))) void simplex_wave_kernel(SolveArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x;
@@ -610,7 +610,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
                     if (cj2 >= n) { cj2 -= n; pos += wrap; }
                 }
             } else {
-                constexpr int UB = 16;
+                // (Eight loads in flight for FP32 LPs of up to 64 rows keeps them
+                // within the registers of five wavefronts per SIMD.)
+                constexpr int UB = (sizeof(T) == 4 && RB == 1) ? 8 : 16;
                 for (int f0 = 0; f0 < mn; f0 += 64 * UB) {
                     double av[UB];
                     if (gather) {
