@@ -47,13 +47,20 @@ void parallel_copy(void *dst, const void *src, size_t bytes)
     const size_t step = (bytes + parts - 1) / parts;
     std::vector<std::thread> th;
     th.reserve(parts);
-    for (size_t t = 0; t < parts; ++t) {
-        const size_t lo = t * step, hi = std::min(bytes, lo + step);
-        if (lo >= hi) break;
-        th.emplace_back([=] {
-            std::memcpy(static_cast<char *>(dst) + lo, static_cast<const char *>(src) + lo, hi - lo);
-        });
+    size_t done = 0;  // bytes handed to threads; the calling thread copies the rest
+    try {
+        for (size_t t = 0; t < parts; ++t) {
+            const size_t lo = t * step, hi = std::min(bytes, lo + step);
+            if (lo >= hi) break;
+            th.emplace_back([=] {
+                std::memcpy(static_cast<char *>(dst) + lo, static_cast<const char *>(src) + lo, hi - lo);
+            });
+            done = hi;
+        }
+    } catch (...) {
+        // No thread could be started: the slices not handed out are copied here.
     }
+    if (done < bytes) std::memcpy(static_cast<char *>(dst) + done, static_cast<const char *>(src) + done, bytes - done);
     for (auto &t : th) t.join();
 }
 
