@@ -70,11 +70,14 @@ def test_topk_exact_on_device_scores(torch_ctx):
     flat = mlp.flatten(p).astype(np.float32)
     ctx.mlp_set_params(_dev(torch, flat))
     d = _dirs(4, 513)
-    for k in (1, 20, 48, 120):
+    for k in (1, 20, 48, 64, 65, 120):
         S, T = ctx.mlp_infer(_dev(torch, d), k=k)
         S = S.cpu().numpy()
         np.testing.assert_array_equal(S[:, 5], S[:, 7])
         np.testing.assert_array_equal(T.cpu().numpy(), mlp.topk(S, k))
+        # The top-k alone (no scores written) is the same.
+        _, T2 = ctx.mlp_infer(_dev(torch, d), k=k, scores=False)
+        np.testing.assert_array_equal(T2.cpu().numpy(), T.cpu().numpy())
 
 
 def test_gradients_match_oracle(torch_ctx):
