@@ -600,7 +600,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
             double bm = 0.0, cm = 0.0;
             for (int i = lane; i < m; i += 64) bm = fmax(bm, fabs(b[i]));
             for (int j = lane; j < n; j += 64) cm = fmax(cm, fabs(c[j]));
-            const double bnorm = wave_max(bm), cnorm = wave_max(cm);
+            const double bnorm = wave_max_f(bm), cnorm = wave_max_f(cm);
             const double tol_p = a.tol_feas * (1.0 + bnorm);
             const double tol_d = a.tol_opt * fmax(1.0, cnorm);
             // A basis with more than kl basic structurals (rare: the host sizes kl
@@ -647,11 +647,11 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 }
                 rz = (lane < K) ? sgt * b[tl] : 0.0;
                 cs = (lane < K) ? c[sl] : 0.0;
-                const double amax = wave_max(am);
+                const double amax = wave_max_f(am);
                 wave_sync();
                 for (int p = 0; p < K; ++p) {
                     const double v = (lane < K && pos == kBig) ? fabs(colv) : -1.0;
-                    const double vmax = wave_max(v);
+                    const double vmax = wave_max_f(v);
                     if (!(vmax > 1e-13 * fmax(1.0, amax))) { ok = false; break; }
                     const int pl = __builtin_ctzll(__ballot(v == vmax));
                     if (lane == pl) pos = p;
