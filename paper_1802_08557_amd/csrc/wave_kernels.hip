@@ -665,11 +665,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
             }
         }
         }  // fits
-        const double cnorm = wave_max(fabs(cj));
+        const double cnorm = wave_max_f(fabs(cj));
         double bm = 0.0;
 #pragma unroll
         for (int r = 0; r < RB; ++r) bm = fmax(bm, fabs(bv[r]));
-        const double bnorm = wave_max(bm);
+        const double bnorm = wave_max_f(bm);
         // The registers of F are free again: start loading the next LP.  (The
         // last LP of a wavefront reloads itself, so the loads are unconditional
         // and land in the registers the current LP's came in.)
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
                 }
                 P.d = acc;
                 P.z = zacc;
-                const double dmax = wave_max(lane < N ? fabs(double(acc)) : 0.0);
+                const double dmax = wave_max_f(lane < N ? fabs(double(acc)) : 0.0);
                 const double dscale = fmax(1.0, dmax);
                 const int r = simplex<T, RB>(P, T(a.prm.tol_opt * dscale), a.prm, &enter);
                 P.it1 = P.iters;
