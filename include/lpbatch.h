@@ -158,6 +158,13 @@ typedef struct {
      * LP_INVALID_INPUT in the first pass and sends it to the re-solve.       */
     const int32_t *row_subset;
     int32_t subset_m;    /* rows per LP in row_subset, 1..m[0]                    */
+    /* Preconditioning (not part of the paper's method, which pivots on the LP
+     * as given, Sec. 4): scaling = P > 0 runs P passes of geometric-mean
+     * scaling with power-of-two factors (lp_batch_scale) on a copy of the
+     * batch in context scratch, solves the scaled LPs with every other option
+     * unchanged (tolerances then apply to the scaled data) and maps x back;
+     * status and obj refer to the LP as given.  0: off; at most 64.           */
+    int32_t scaling;
 } lp_options;
 
 #define LP_FLAG_SYNC 1u        /* wait for the stream before returning            */
@@ -235,6 +242,34 @@ int lp_ctx_kernel_times(lp_ctx *ctx, const char **names, float *ms, int cap);
  * the table holds (entries may be NULL to count), or a negative LP_ERR_* code.
  */
 int lp_ctx_tuning(lp_ctx *ctx, int32_t *entries, int cap);
+
+/*
+ * lp_batch_scale -- geometric-mean scaling with power-of-two factors, the
+ * preconditioning behind lp_options.scaling (the paper applies none: its
+ * tableau is built from the LP as given, Sec. 4).
+ *
+ * For LP k (layout as in lp_batch_solve) let E_ij = floor(log2 |a_ij|) over
+ * the finite non-zero entries.  Starting from s_j = 0, each of `passes`
+ * passes sets, for every row with such entries,
+ *     r_i = -floor((max_j (E_ij + s_j) + min_j (E_ij + s_j) + 1) / 2),
+ * then s_j the same way down every column with the new r_i; rows and columns
+ * without entries get 0, every exponent is clamped to [-128, 128].  Outputs:
+ *     A_out[ij] = a_ij 2^(r_i + s_j),  b_out[i] = b_i 2^r_i,  c_out[j] = c_j 2^s_j,
+ *     row_exp[i] = r_i,  col_exp[j] = s_j,
+ * which is the same LP in x'_j = x_j / 2^s_j (exact: powers of two round
+ * nothing unless a value leaves the double range).
+ * A, b, c, A_out, b_out, c_out, row_exp, col_exp: DEVICE pointers, same
+ * layout as the inputs (row_exp [sum m_k], col_exp [sum n_k]); with
+ * shared = 1 (every m[k], n[k] equal) A and b hold one LP, c is [num][n[0]],
+ * and the exponents are those of the one A ([m[0]], [n[0]]).  m, n: HOST
+ * int32 [num_lps].  passes: 0..64 (0 copies with zero exponents).  Outputs
+ * must not overlap the inputs.  Queued on stream (NULL: null stream); uneven
+ * batches wait for a small upload of their shapes first.  Returns LP_OK or
+ * LP_ERR_ARG / LP_ERR_NOMEM / LP_ERR_HIP.
+ */
+int lp_batch_scale(lp_ctx *ctx, int64_t num_lps, const double *A, const double *b, const double *c,
+                   const int32_t *m, const int32_t *n, int32_t passes, int32_t shared, double *A_out,
+                   double *b_out, double *c_out, int32_t *row_exp, int32_t *col_exp, void *stream);
 
 /*
  * lp_hyperbox_support -- LPs whose feasible set is a hyper-rectangle, in

@@ -10,6 +10,8 @@ Contents
   * ``brute``      -- vertex enumeration for tiny LPs (an independent check).
   * ``certificate``-- KKT / strong-duality check of an optimal basis.
   * ``hyperbox``   -- the closed-form box LP of Eq. (7), Sec. 5.6.
+  * ``scaling``    -- power-of-two geometric-mean scaling (not in the paper;
+                      the reference for the optional preconditioning).
 """
 from __future__ import annotations
 

@@ -143,6 +143,7 @@ struct lp_ctx {
     int num_cu = 0;
     int max_lds = 0;
     lpb::DevBuf scratch, meta, counters;
+    lpb::DevBuf scaled, scale_meta;  // lp_options.scaling: scaled copy, shapes
     std::vector<lpb::KernelTime> times;
     std::vector<hipEvent_t> event_pool;
     size_t events_used = 0;

@@ -165,6 +165,17 @@ hipError_t mlp_configure();
 hipError_t launch_hyperbox(int64_t num, int n, const double *lo, const double *hi, const double *l,
                            int shared_box, double *value, double *x, hipStream_t s);
 
+// Power-of-two scaling (scale_kernels.hip).  um/un: uniform shape, or 0 with
+// the per-LP shape and offset arrays; c_out may be NULL (c left alone).
+// host_m / host_n: the shapes in host memory (read to size the launch).
+hipError_t launch_scale(int64_t num, int32_t um, int32_t un, const int32_t *m, const int32_t *n,
+                        const int64_t *aoff, const int64_t *roff, const int64_t *coff, const int32_t *host_m,
+                        const int32_t *host_n, int32_t passes, const double *A, const double *b, const double *c,
+                        double *A_out, double *b_out, double *c_out, int32_t *rexp, int32_t *cexp, hipStream_t s);
+// out[i] = in[i] * 2^e[i] (period 0) or 2^e[i % period]; in may equal out.
+hipError_t launch_ldexp(int64_t count, const double *in, const int32_t *e, int64_t period, double *out,
+                        hipStream_t s);
+
 // Bland index convention shared by every kernel: structural j -> j, the
 // slack/surplus of row i -> n + i, the artificial of row i -> n + m + i.
 

@@ -348,6 +348,109 @@ int queue_binned(lp_ctx *ctx, const Plan &P, const lpb::SolveArgs &a, const lp_o
     return LP_OK;
 }
 
+// Shapes of a batch for scaling: validated like lp_batch_solve_ex; sizes of
+// A, b and c (shared: the one LP's A and b).
+struct ScaleShape {
+    bool uniform = true;
+    int64_t sa = 0, sr = 0, sc = 0;
+};
+
+int scale_shape(int64_t num, const int32_t *m, const int32_t *n, bool shared, ScaleShape &S)
+{
+    for (int64_t k = 0; k < num; ++k) {
+        if (m[k] < 1 || n[k] < 1)
+            return fail(LP_ERR_ARG, "LP %lld has m=%d n=%d (both must be >= 1)", (long long)k, m[k], n[k]);
+        if (m[k] > 1000000 || n[k] > 1000000)
+            return fail(LP_ERR_ARG, "LP %lld is too large (m=%d n=%d)", (long long)k, m[k], n[k]);
+        S.uniform = S.uniform && m[k] == m[0] && n[k] == n[0];
+        S.sa += int64_t(m[k]) * n[k];
+        S.sr += m[k];
+        S.sc += n[k];
+        if (S.sa > (int64_t(1) << 60)) return fail(LP_ERR_ARG, "batch size overflows");
+    }
+    if (shared && !S.uniform) return fail(LP_ERR_ARG, "shared = 1 needs every m[k] and every n[k] equal");
+    if (shared) {
+        S.sa = int64_t(m[0]) * n[0];
+        S.sr = m[0];
+    }
+    return LP_OK;
+}
+
+int scale_batch(lp_ctx *ctx, int64_t num, const double *A, const double *b, const double *c, const int32_t *m,
+                const int32_t *n, int32_t passes, bool shared, const ScaleShape &S, double *A_out,
+                double *b_out, double *c_out, int32_t *rexp, int32_t *cexp, hipStream_t stream, bool timing)
+{
+    Timer t(ctx, timing, stream, "scale_fp64");
+    if (shared) {
+        // One A: its factors, then every LP's c by the column factors.
+        HIP_TRY(lpb::launch_scale(1, m[0], n[0], nullptr, nullptr, nullptr, nullptr, nullptr, m, n, passes, A, b,
+                                  c, A_out, b_out, nullptr, rexp, cexp, stream));
+        HIP_TRY(lpb::launch_ldexp(num * n[0], c, cexp, n[0], c_out, stream));
+    } else if (S.uniform) {
+        HIP_TRY(lpb::launch_scale(num, m[0], n[0], nullptr, nullptr, nullptr, nullptr, nullptr, m, n, passes, A, b,
+                                  c, A_out, b_out, c_out, rexp, cexp, stream));
+    } else {
+        const size_t bytes = size_t(num) * (2 * sizeof(int32_t) + 3 * sizeof(int64_t));
+        int rc = ctx->scale_meta.ensure(bytes);
+        if (rc != LP_OK) return rc;
+        std::vector<char> host(bytes);
+        int32_t *hm = reinterpret_cast<int32_t *>(host.data());
+        int32_t *hn = hm + num;
+        int64_t *ha = reinterpret_cast<int64_t *>(hn + num);
+        int64_t *hr = ha + num, *hc = hr + num;
+        int64_t oa = 0, orr = 0, oc = 0;
+        for (int64_t k = 0; k < num; ++k) {
+            hm[k] = m[k]; hn[k] = n[k];
+            ha[k] = oa; hr[k] = orr; hc[k] = oc;
+            oa += int64_t(m[k]) * n[k]; orr += m[k]; oc += n[k];
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->scale_meta.p, host.data(), bytes, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));  // the host staging buffer goes away
+        const int32_t *dm = ctx->scale_meta.as<int32_t>();
+        const int64_t *da = reinterpret_cast<const int64_t *>(dm + 2 * num);
+        HIP_TRY(lpb::launch_scale(num, 0, 0, dm, dm + num, da, da + num, da + 2 * num, m, n, passes, A, b, c,
+                                  A_out, b_out, c_out, rexp, cexp, stream));
+    }
+    t.done();
+    return LP_OK;
+}
+
+// lp_batch_solve_ex with opts.scaling > 0: scale into context scratch, solve
+// the scaled batch, map x back (x_j = x'_j 2^s_j; obj and status carry over).
+int solve_scaled(lp_ctx *ctx, int64_t num, const double *A, const double *b, const double *c, const int8_t *sense,
+                 const int32_t *m, const int32_t *n, int32_t *status, double *x, double *obj,
+                 const lp_options &opts)
+{
+    const bool shared = opts.shared != 0;
+    ScaleShape S;
+    int rc = scale_shape(num, m, n, shared, S);
+    if (rc != LP_OK) return rc;
+    const int64_t nc = shared ? num * int64_t(n[0]) : S.sc;
+    const size_t oA = 0, ob = oA + lpb::align16(8 * size_t(S.sa)), oc = ob + lpb::align16(8 * size_t(S.sr)),
+                 orx = oc + lpb::align16(8 * size_t(nc)), ocx = orx + lpb::align16(4 * size_t(S.sr)),
+                 end = ocx + lpb::align16(4 * size_t(S.sc));
+    rc = ctx->scaled.ensure(end);
+    if (rc != LP_OK) return rc;
+    double *As = ctx->scaled.as<double>(oA), *bs = ctx->scaled.as<double>(ob), *cs = ctx->scaled.as<double>(oc);
+    int32_t *rx = ctx->scaled.as<int32_t>(orx), *cx = ctx->scaled.as<int32_t>(ocx);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(opts.stream);
+    const bool timing = (opts.flags & LP_FLAG_TIME_KERNELS) != 0;
+    rc = scale_batch(ctx, num, A, b, c, m, n, opts.scaling, shared, S, As, bs, cs, rx, cx, stream, timing);
+    if (rc != LP_OK) return rc;
+    lp_options o = opts;
+    o.scaling = 0;
+    o.flags &= ~LP_FLAG_SYNC;
+    rc = lp_batch_solve_ex(ctx, num, As, bs, cs, sense, m, n, status, x, obj, &o);
+    if (rc != LP_OK) return rc;
+    {
+        Timer t(ctx, timing, stream, "unscale_x");
+        HIP_TRY(lpb::launch_ldexp(nc, x, cx, shared ? n[0] : 0, x, stream));
+        t.done();
+    }
+    if (opts.flags & LP_FLAG_SYNC) HIP_TRY(hipStreamSynchronize(stream));
+    return LP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -404,6 +507,8 @@ void lp_ctx_destroy(lp_ctx *ctx)
     (void)hipDeviceSynchronize();
     ctx->scratch.release();
     ctx->meta.release();
+    ctx->scaled.release();
+    ctx->scale_meta.release();
     ctx->counters.release();
     lpb::MlpState &M = ctx->mlp;
     for (lpb::DevBuf *d : {&M.params, &M.params16, &M.adam_m, &M.adam_v, &M.grads, &M.act, &M.misc})
@@ -438,10 +543,15 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         return fail(LP_ERR_ARG, "block_threads must be 0, 64, 128, 256 or 512");
     if (opts.placement < 0 || opts.placement > LP_PLACE_HBM)
         return fail(LP_ERR_ARG, "unknown placement %d", opts.placement);
+    if (opts.scaling < 0 || opts.scaling > 64) return fail(LP_ERR_ARG, "scaling must lie in 0..64 (got %d)", opts.scaling);
     if (num_lps == 0) return LP_OK;
     if (!A || !b || !c || !sense || !m || !n || !status || !x || !obj)
         return fail(LP_ERR_ARG, "a batch pointer is NULL");
     if (num_lps > INT32_MAX) return fail(LP_ERR_ARG, "num_lps exceeds 2^31-1");
+    if (opts.scaling > 0) {
+        DeviceGuard g(ctx->device);
+        return solve_scaled(ctx, num_lps, A, b, c, sense, m, n, status, x, obj, opts);
+    }
 
     // Shapes (host arrays) and the uniform-shape shortcut.
     Plan P;
@@ -764,6 +874,24 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     ctx->counters_dirty = false;
     if (opts.flags & LP_FLAG_SYNC) HIP_TRY(hipStreamSynchronize(stream));
     return LP_OK;
+}
+
+int lp_batch_scale(lp_ctx *ctx, int64_t num_lps, const double *A, const double *b, const double *c,
+                   const int32_t *m, const int32_t *n, int32_t passes, int32_t shared, double *A_out,
+                   double *b_out, double *c_out, int32_t *row_exp, int32_t *col_exp, void *stream)
+{
+    if (!ctx) return fail(LP_ERR_ARG, "lp_batch_scale: ctx is NULL");
+    if (num_lps < 0) return fail(LP_ERR_ARG, "num_lps is negative (%lld)", (long long)num_lps);
+    if (passes < 0 || passes > 64) return fail(LP_ERR_ARG, "passes must lie in 0..64 (got %d)", passes);
+    if (num_lps == 0) return LP_OK;
+    if (!A || !b || !c || !m || !n || !A_out || !b_out || !c_out || !row_exp || !col_exp)
+        return fail(LP_ERR_ARG, "lp_batch_scale: a pointer is NULL");
+    ScaleShape S;
+    int rc = scale_shape(num_lps, m, n, shared != 0, S);
+    if (rc != LP_OK) return rc;
+    DeviceGuard g(ctx->device);
+    return scale_batch(ctx, num_lps, A, b, c, m, n, passes, shared != 0, S, A_out, b_out, c_out, row_exp, col_exp,
+                       reinterpret_cast<hipStream_t>(stream), false);
 }
 
 int lp_hyperbox_support(lp_ctx *ctx, int64_t num, int32_t n, const double *lo, const double *hi,

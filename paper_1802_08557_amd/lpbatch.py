@@ -29,7 +29,7 @@ EXPORTS = ("lp_batch_solve", "lp_ctx_create", "lp_ctx_destroy", "lp_options_init
            "lp_batch_solve_ex", "lp_ctx_kernel_times", "lp_last_error",
            "lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
            "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
-           "lp_hyperbox_support", "lp_ctx_tuning", "lp_batch_solve_host")
+           "lp_hyperbox_support", "lp_ctx_tuning", "lp_batch_solve_host", "lp_batch_scale")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NUM_PARAMS = 20, 256, 120, 102008
 
 
@@ -40,7 +40,8 @@ class LPOptions(ctypes.Structure):
                 ("placement", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("stats", ctypes.c_void_p), ("stream", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("shared", ctypes.c_int32),
-                ("row_subset", ctypes.c_void_p), ("subset_m", ctypes.c_int32)]
+                ("row_subset", ctypes.c_void_p), ("subset_m", ctypes.c_int32),
+                ("scaling", ctypes.c_int32)]
 
 
 class LPBatchError(RuntimeError):
@@ -91,6 +92,8 @@ def load():
     lib.lp_ctx_tuning.restype = i32
     lib.lp_batch_solve_host.argtypes = [vp, i64] + [vp] * 9 + [ctypes.POINTER(LPOptions), i64]
     lib.lp_batch_solve_host.restype = i32
+    lib.lp_batch_scale.argtypes = [vp, i64] + [vp] * 5 + [ctypes.c_int32, ctypes.c_int32] + [vp] * 6
+    lib.lp_batch_scale.restype = i32
     for nm in ("lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
                "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
            "lp_hyperbox_support", "lp_ctx_tuning"):
@@ -189,10 +192,10 @@ class Context:
     def solve(self, batch: DeviceBatch, *, precision=PREC_FP64, max_iters=0, tol_piv=0.0,
               tol_opt=0.0, tol_feas=0.0, k_deg=50, placement=PLACE_AUTO, block_threads=0,
               stats=False, stream=None, sync=False, time_kernels=False, out=None,
-              row_subset=None, autotune=False) -> Solution:
+              row_subset=None, autotune=False, scaling=0) -> Solution:
         """Queue lp_batch_solve_ex on `stream` (default: torch's current stream).
         row_subset: int32 device tensor [N, subset_m] for a screened solve of a
-        shared batch."""
+        shared batch.  scaling: passes of power-of-two scaling (0: off)."""
         import torch
         dev = batch.A.device
         N = batch.num_lps
@@ -215,6 +218,7 @@ class Context:
         o.flags = ((FLAG_SYNC if sync else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
                    | (FLAG_AUTOTUNE if autotune else 0))
         o.shared = 1 if batch.shared else 0
+        o.scaling = scaling
         if row_subset is not None:
             if row_subset.dim() != 2 or row_subset.shape[0] != N:
                 raise ValueError("row_subset must be [num_lps, subset_m]")
@@ -229,8 +233,35 @@ class Context:
             _ptr(status), _ptr(x), _ptr(obj), ctypes.byref(o)))
         return Solution(status, x, obj, st)
 
+    def scale(self, batch: DeviceBatch, passes: int, stream=None):
+        """lp_batch_scale: (A', b', c', row_exp, col_exp) as device tensors,
+        queued on `stream` (default: torch's current stream)."""
+        import torch
+        dev = batch.A.device
+        N = batch.num_lps
+        m = np.ascontiguousarray(batch.m, np.int32)
+        n = np.ascontiguousarray(batch.n, np.int32)
+        if batch.shared:
+            rows, cols, nc = int(m[0]), int(n[0]), N * int(n[0])
+        else:
+            rows, cols = int(m.astype(np.int64).sum()), int(n.astype(np.int64).sum())
+            nc = cols
+        A2 = torch.empty(batch.A.numel(), dtype=torch.float64, device=dev)
+        b2 = torch.empty(batch.b.numel(), dtype=torch.float64, device=dev)
+        c2 = torch.empty(nc, dtype=torch.float64, device=dev)
+        rexp = torch.empty(rows, dtype=torch.int32, device=dev)
+        cexp = torch.empty(cols, dtype=torch.int32, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(self.lib.lp_batch_scale(
+            self.handle, N, _ptr(batch.A), _ptr(batch.b), _ptr(batch.c),
+            m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p), int(passes),
+            1 if batch.shared else 0, _ptr(A2), _ptr(b2), _ptr(c2), _ptr(rexp), _ptr(cexp),
+            ctypes.c_void_p(stream.cuda_stream)))
+        return A2, b2, c2, rexp, cexp
+
     def solve_host(self, A, b, c, sense, m, n, *, precision=PREC_FP64, chunk_lps=0, out=None,
-                   time_kernels=False):
+                   time_kernels=False, scaling=0):
         """lp_batch_solve_host on a batch in host memory: A, b, c, sense are
         numpy arrays or CPU torch tensors (pinned tensors are copied directly,
         pageable memory is staged by the library); m, n numpy int32.  Returns
@@ -258,6 +289,7 @@ class Context:
         o = LPOptions()
         self.lib.lp_options_init(ctypes.byref(o))
         o.precision = precision
+        o.scaling = scaling
         o.flags = FLAG_TIME_KERNELS if time_kernels else 0
         _check(self.lib.lp_batch_solve_host(
             self.handle, N, host_ptr(A, "float64", cells, "A"), host_ptr(b, "float64", rows, "b"),

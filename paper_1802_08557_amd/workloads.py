@@ -28,6 +28,8 @@ batches stand in for them):
                   the free variable so every LP is in the x >= 0 form.
   phase1_batch    test-only: feasible LPs whose >= rows have a positive rhs,
                   so Phase I is needed and succeeds.
+  rescaled        test-only: any batch with rows and columns multiplied by
+                  random powers of ten (badly scaled, same optima).
 Batch-sized draws use numpy's PCG64 in chunks of 10,000 LPs, each chunk from
 ``SeedSequence(seed).spawn(ceil(N / 1e4))``.
 """
@@ -177,6 +179,26 @@ def phase1_batch(N: int, m: int, n: int, seed: int, frac_ge: float = 0.3, frac_e
     return Batch(A.reshape(-1), b.reshape(-1), c.reshape(-1), sense.reshape(-1),
                  np.full(N, m, np.int32), np.full(N, n, np.int32), f"phase1_{m}x{n}_x{N}",
                  dict(seed=seed))
+
+
+def rescaled(batch: Batch, seed: int, spread: float = 3.0) -> Batch:
+    """Test-only badly scaled copy of a batch: every row of every LP (its A row
+    and b_i) times 10^u and every column (its A column and c_j) times 10^v,
+    u, v ~ U[-spread, spread] drawn per row and per column.  Row factors keep
+    the feasible set, column factors substitute x_j -> x_j / 10^v: the LPs keep
+    their status and optimal value."""
+    rng = np.random.default_rng(seed)
+    aoff, roff, coff = batch.offsets()
+    A, b, c = batch.A.copy(), batch.b.copy(), batch.c.copy()
+    for k in range(batch.num_lps):
+        m, n = int(batch.m[k]), int(batch.n[k])
+        rf = 10.0 ** rng.uniform(-spread, spread, size=m)
+        cf = 10.0 ** rng.uniform(-spread, spread, size=n)
+        A[aoff[k]:aoff[k + 1]] = (A[aoff[k]:aoff[k + 1]].reshape(m, n) * rf[:, None] * cf[None, :]).ravel()
+        b[roff[k]:roff[k + 1]] *= rf
+        c[coff[k]:coff[k + 1]] *= cf
+    return Batch(A, b, c, batch.sense.copy(), batch.m.copy(), batch.n.copy(),
+                 batch.name + f"_rescaled{spread:g}", dict(batch.meta, rescale_seed=seed))
 
 
 # ---- support-function batches over a fixed polytope ------------------------

@@ -45,7 +45,24 @@ def test_options_defaults(lib):
     o.precision = 7
     lib.lp_options_init(ctypes.byref(o))
     assert o.precision == 0 and o.k_deg == 50 and o.max_iters == 0 and o.flags == 0
-    assert o.stats is None and o.stream is None
+    assert o.stats is None and o.stream is None and o.scaling == 0
+
+
+def test_options_layout_matches_the_header(tmp_path):
+    # The ctypes mirror of lp_options has the C struct's size and offsets.
+    from paper_1802_08557_amd.lpbatch import LPOptions
+    fields = [f[0] for f in LPOptions._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lpbatch.h"\nint main(void){'
+                   'printf("%zu", sizeof(lp_options));'
+                   + "".join(f'printf(" %zu", offsetof(lp_options, {f}));' for f in fields)
+                   + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(LPOptions)
+    assert got[1:] == [getattr(LPOptions, f).offset for f in fields]
 
 
 def test_null_context_and_bad_arguments_are_errors(lib):
@@ -54,6 +71,7 @@ def test_null_context_and_bad_arguments_are_errors(lib):
     assert "ctx" in lpbatch.last_error()
     assert lib.lp_ctx_create(None, 0) == lpbatch.LP_ERR_ARG
     assert lib.lp_ctx_kernel_times(None, None, None, 0) == lpbatch.LP_ERR_ARG
+    assert lib.lp_batch_scale(None, 1, *([None] * 5), 4, 0, *([None] * 6)) == lpbatch.LP_ERR_ARG
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd") and os.access("/dev/kfd", os.R_OK),
