@@ -288,6 +288,50 @@ def host_pipeline_block(batch, ctx, reps=3):
     return res
 
 
+def scaling_block(ctx, passes=4, reps=3, spread=3.0):
+    """Optional scaling on a badly scaled copy of the benchmark batch (every
+    row and column of every LP times 10^U[-spread, spread]; same optima): the
+    solve with and without lp_options.scaling, in FP64 and FP32 + certificate.
+    Per case: ms per solve (scale kernel included), pivots per LP, FP64
+    re-solves; and the scale kernel's rate against HBM (algorithmic bytes:
+    read A, b, c, write A', b', c' and the exponents)."""
+    import torch
+    from paper_1802_08557_amd import workloads as W
+    from paper_1802_08557_amd.lpbatch import DeviceBatch, PREC_FP32_CERT64, PREC_FP64
+    base = W.config1()
+    bt = W.rescaled(base, seed=7, spread=spread)
+    db = DeviceBatch.from_host(bt)
+    N = bt.num_lps
+    m, n = int(bt.m[0]), int(bt.n[0])
+    res = dict(workload=f"rescaled_{m}x{n}_x{N}", spread=spread, passes=passes)
+    for pname, prec in (("fp64", PREC_FP64), ("fp32c", PREC_FP32_CERT64)):
+        for sc in (0, passes):
+            sol = ctx.solve(db, precision=prec, scaling=sc, stats=True)
+            torch.cuda.synchronize()
+            ctx.kernel_times()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                sol = ctx.solve(db, precision=prec, scaling=sc, stats=True, time_kernels=True)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            kt = {}
+            for name, ms in ctx.kernel_times():
+                kt[name] = kt.get(name, 0.0) + ms / reps
+            st = sol.stats.cpu().numpy()
+            key = f"{pname}_{'scaled' if sc else 'unscaled'}"
+            res[key] = dict(ms=t * 1e3, lps_per_s=N / t,
+                            pivots_per_lp=float((st[:, 0].astype(np.int64) + st[:, 1]).mean()),
+                            fp64_resolves=int((st[:, 3] >= 1).sum()),
+                            kernels_ms={k: round(v, 4) for k, v in kt.items()})
+            if sc and "scale_fp64" in kt:
+                nbytes = N * (16 * m * n + 20 * (m + n))
+                res["scale_kernel"] = dict(ms=kt["scale_fp64"], algorithmic_bytes=nbytes,
+                                           gb_per_s=nbytes / (kt["scale_fp64"] * 1e-3) / 1e9,
+                                           frac_of_hbm=nbytes / (kt["scale_fp64"] * 1e-3) / 8e12)
+    res["note"] = "optional preconditioning (default off); accuracy is checked in the tests, not here"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +357,8 @@ def main():
     ap.add_argument("--warm-steps", type=int, default=10)
     ap.add_argument("--warm-sample", type=int, default=20_000)
     ap.add_argument("--no-host", action="store_true", help="skip the host-resident pipeline leg")
+    ap.add_argument("--no-scaling", action="store_true", help="skip the scaling comparison")
+    ap.add_argument("--scaling-only", action="store_true", help="print only the scaling comparison")
     args = ap.parse_args()
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
@@ -327,6 +373,11 @@ def main():
     from paper_1802_08557_amd.lpbatch import DeviceBatch
     if args.warm_only:
         print(json.dumps(warm_start_block(args)), flush=True)
+        return 0
+    if args.scaling_only:
+        ctx = lpbatch.Context(0)
+        print(json.dumps(scaling_block(ctx)), flush=True)
+        ctx.close()
         return 0
 
     batch = workload(args.config)
@@ -439,6 +490,11 @@ def main():
             rec["host_pipeline"] = host_pipeline_block(batch, ctx)
         except Exception as e:  # the main measurement stands on its own
             rec["host_pipeline"] = dict(error=f"{type(e).__name__}: {e}")
+    if not args.no_scaling and not args.graph and args.config == 1:
+        try:
+            rec["lp_scaling"] = scaling_block(ctx)
+        except Exception as e:  # the main measurement stands on its own
+            rec["lp_scaling"] = dict(error=f"{type(e).__name__}: {e}")
     if not args.no_warm and args.config == 1:
         try:
             rec["warm_start"] = warm_start_block(args)
