@@ -45,7 +45,7 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("tol_piv", ctypes.c_double), ("tol_opt", ctypes.c_double),
                 ("tol_feas", ctypes.c_double), ("k_deg", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("pricing", ctypes.c_int32)]
 
 
 _lib = None
@@ -78,9 +78,10 @@ def _p(a, dt):
 
 
 def solve(A, b, c, sense, m, n, *, tol_piv=1e-9, tol_opt=1e-9, tol_feas=1e-9,
-          k_deg=50, max_iters=0, threads=1) -> Result:
+          k_deg=50, max_iters=0, threads=1, pricing=0) -> Result:
     """Solve a batch of LPs (max c^T x, A x {<=,>=,=} b, x >= 0) stored back to
-    back: A row-major per LP, b/sense per row, c per column, m/n per LP."""
+    back: A row-major per LP, b/sense per row, c per column, m/n per LP.
+    pricing: 0 Dantzig (the paper's Step 1), 1 steepest edge."""
     lib = _load()
     m_, pm = _p(np.atleast_1d(m), np.int32)
     n_, pn = _p(np.atleast_1d(n), np.int32)
@@ -97,7 +98,7 @@ def solve(A, b, c, sense, m, n, *, tol_piv=1e-9, tol_opt=1e-9, tol_feas=1e-9,
     x = np.empty(int(n_.sum()), np.float64)
     basis = np.empty(int(m_.sum()), np.int32)
     stats = np.empty((N, 3), np.int32)
-    prm = _Params(tol_piv, tol_opt, tol_feas, k_deg, max_iters)
+    prm = _Params(tol_piv, tol_opt, tol_feas, k_deg, max_iters, pricing)
     rc = lib.oracle_solve_batch(N, pA, pb, pc, ps, pm, pn, ctypes.byref(prm), int(threads),
                                 status.ctypes.data_as(ctypes.c_void_p),
                                 x.ctypes.data_as(ctypes.c_void_p),
@@ -110,7 +111,7 @@ def solve(A, b, c, sense, m, n, *, tol_piv=1e-9, tol_opt=1e-9, tol_feas=1e-9,
 
 
 def solve_traced(A, b, c, sense=None, *, tol_piv=1e-9, tol_opt=1e-9, tol_feas=1e-9,
-                 k_deg=50, max_iters=0, max_snapshots=64):
+                 k_deg=50, max_iters=0, max_snapshots=64, pricing=0):
     """Solve one LP and return (Result, snapshots [k, m+1, ncol+1]): the whole
     tableau after every pricing of an objective row and after every pivot."""
     lib = _load()
@@ -123,7 +124,7 @@ def solve_traced(A, b, c, sense=None, *, tol_piv=1e-9, tol_opt=1e-9, tol_feas=1e
     ld_max = n + 2 * m + 1
     buf = np.zeros(max_snapshots * (m + 1) * ld_max)
     ncol = ctypes.c_int32(); nsnap = ctypes.c_int32()
-    prm = _Params(tol_piv, tol_opt, tol_feas, k_deg, max_iters)
+    prm = _Params(tol_piv, tol_opt, tol_feas, k_deg, max_iters, pricing)
     v = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     lib.oracle_solve_traced.restype = ctypes.c_int
     st = lib.oracle_solve_traced(ctypes.c_int(m), ctypes.c_int(n), v(A), v(b), v(c), v(sense),

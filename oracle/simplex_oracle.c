@@ -69,6 +69,7 @@ typedef struct {
     double tol_feas;  /* relative tolerance on the Phase I optimum              */
     int32_t k_deg;    /* consecutive degenerate pivots before Bland's rule; <=0: never */
     int32_t max_iters;/* pivot cap over both phases; <= 0: 50 * (m + #columns)  */
+    int32_t pricing;  /* 0: Dantzig (the paper's Step 1); 1: steepest edge      */
 } oracle_params;
 
 typedef struct {
@@ -164,7 +165,10 @@ static int simplex_loop(tableau *tb, double eps_opt, const oracle_params *p,
         if (*iters >= cap)
             return OR_ITERATION_LIMIT;
         const int bland_mode = (p->k_deg > 0 && degenerate_run >= p->k_deg);
-        /* Step 1: entering column. */
+        /* Step 1: entering column.  Dantzig: the largest d_j.  Steepest edge
+         * (optional, not the paper's rule): the largest d_j^2 / (1 + sum_i t_ij^2)
+         * over the live constraint rows -- the squared rate of objective gain
+         * per unit length of the edge that column j opens. */
         int e = -1;
         double best = 0.0;
         for (int j = 0; j < tb->ncol; ++j) {
@@ -174,7 +178,14 @@ static int simplex_loop(tableau *tb, double eps_opt, const oracle_params *p,
             if (!(d > eps_opt))
                 continue;
             if (bland_mode) { e = j; break; }           /* columns are in Bland order */
-            if (e < 0 || d > best) { e = j; best = d; } /* strict: ties keep the smaller index */
+            double score = d;
+            if (p->pricing == 1) {
+                double w = 1.0;
+                for (int i = 0; i < tb->m; ++i)
+                    if (!tb->row_dead[i]) w += T_(tb, i, j) * T_(tb, i, j);
+                score = d * d / w;
+            }
+            if (e < 0 || score > best) { e = j; best = score; } /* strict: ties keep the smaller index */
         }
         if (e < 0)
             return OR_OPTIMAL;

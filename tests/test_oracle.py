@@ -289,3 +289,58 @@ def test_workload_invariants():
         basis = res.basis[k * 120:(k + 1) * 120]
         slack_basic = np.sum(basis >= 40)
         assert 120 - slack_basic == 20
+
+
+# ------------------------------------------------- steepest-edge pricing (optional)
+
+def test_steepest_edge_enters_the_steepest_column():
+    """max 3x1 + 2x2, 10x1 + x2 <= 10, x1 + x2 <= 4.  Dantzig enters x1 (d = 3 > 2),
+    reaching z = 3; steepest edge scores d^2 / (1 + |column|^2): x1 9/102, x2 4/3,
+    so x2 enters at row 2 (ratio 4 < 10) and z = 8.  Both end at (2/3, 10/3), z = 26/3."""
+    A = np.array([[10.0, 1.0], [1.0, 1.0]])
+    for pricing, z1 in ((0, 3.0), (1, 8.0)):
+        r, snaps = oracle.solve_traced(A, [10.0, 4.0], [3.0, 2.0], pricing=pricing)
+        assert r.status[0] == oracle.OPTIMAL
+        assert abs(snaps[1][-1, -1]) == pytest.approx(z1, abs=1e-12)
+        assert r.obj[0] == pytest.approx(26.0 / 3.0, abs=1e-12)
+        np.testing.assert_allclose(r.x, [2.0 / 3.0, 10.0 / 3.0], atol=1e-12)
+
+
+def test_steepest_edge_weight_counts_the_unit_term():
+    """max x1 + 1.9x2, x1 + 2x2 <= 4.  With weights 1 + |column|^2 the scores are
+    1/2 and 3.61/5, so x2 enters first and x1 second (2 pivots); a weight without
+    the 1 would score 1 and 3.61/4 and finish in one pivot."""
+    r = oracle.solve_one(np.array([[1.0, 2.0]]), [4.0], [1.0, 1.9], pricing=1)
+    assert r.status[0] == oracle.OPTIMAL and r.obj[0] == pytest.approx(4.0, abs=1e-12)
+    assert list(r.stats[0, :2]) == [0, 2]
+
+
+@pytest.mark.parametrize("n", range(2, 9))
+def test_steepest_edge_solves_klee_minty_in_one_pivot(n):
+    """On the Klee-Minty cube above, column n has d = 1 and weight 2 (score 1/2),
+    column j < n has d = 10^(n-j) and weight 2 + 4 sum_k 100^k, score < 1/4; x_n
+    enters at row n with x_n = 100^(n-1), which is the optimum (every other
+    reduced cost is then negative): one pivot instead of 2^n - 1."""
+    A, b, c = _klee_minty(n)
+    r = oracle.solve_one(A, b, c, pricing=1)
+    assert r.status[0] == oracle.OPTIMAL
+    assert r.obj[0] == pytest.approx(100.0 ** (n - 1), rel=1e-12)
+    assert list(r.stats[0, :2]) == [0, 1]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_steepest_edge_reaches_the_brute_force_optimum(seed):
+    """Any pricing rule that only picks improving columns ends at the same
+    status and optimum: vertex enumeration on random tiny LPs of all senses."""
+    g = np.random.default_rng(7000 + seed)
+    for _ in range(50):
+        m, n = int(g.integers(1, 5)), int(g.integers(1, 5))
+        A = np.round(g.normal(size=(m, n)), 2)
+        b = np.round(g.uniform(-2, 6, size=m), 2)
+        c = np.round(g.normal(size=n), 2)
+        sense = g.integers(0, 3, size=m).astype(np.int8)
+        st, z = brute_force(A, b, c, sense)
+        r = oracle.solve_one(A, b, c, sense, pricing=1)
+        assert r.status[0] == st
+        if st == oracle.OPTIMAL:
+            assert r.obj[0] == pytest.approx(z, rel=1e-9, abs=1e-9)
