@@ -165,7 +165,16 @@ typedef struct {
      * unchanged (tolerances then apply to the scaled data) and maps x back;
      * status and obj refer to the LP as given.  0: off; at most 64.           */
     int32_t scaling;
+    /* Step 1's rule (lp_pricing).  LP_PRICE_DANTZIG: the largest reduced cost
+     * d_j, the paper's rule.  LP_PRICE_STEEPEST_EDGE (not in the paper): the
+     * largest d_j^2 / (1 + sum_i t_ij^2) over the live rows of the current
+     * tableau -- the gain per unit length of the edge column j opens, computed
+     * exactly from the tableau at every pricing.  Both hand over to Bland's
+     * rule after k_deg degenerate pivots.                                     */
+    int32_t pricing;
 } lp_options;
+
+typedef enum { LP_PRICE_DANTZIG = 0, LP_PRICE_STEEPEST_EDGE = 1 } lp_pricing;
 
 #define LP_FLAG_SYNC 1u        /* wait for the stream before returning            */
 #define LP_FLAG_TIME_KERNELS 2u /* record HIP events around each kernel launched  */

@@ -16,6 +16,7 @@ struct SolveParams {
     double tol_feas;   // Phase I optimum below -tol_feas * (1 + |b|_inf) means infeasible
     int32_t k_deg;     // consecutive degenerate pivots before Bland's rule; <= 0: never
     int32_t max_iters; // pivot cap over both phases; <= 0: 50 * (m + #columns)
+    int32_t pricing;   // 0: Dantzig; 1: steepest edge (d_j^2 / (1 + |column j|^2))
 };
 
 // Everything one launch of the simplex kernel needs.  Device pointers unless noted.

@@ -40,6 +40,7 @@ lpb::SolveParams fill_params(const lp_options &o, bool fp32)
     p.tol_feas = o.tol_feas > 0 ? o.tol_feas : (fp32 ? 1e-6 : 1e-9);
     p.k_deg = o.k_deg == 0 ? 50 : o.k_deg;
     p.max_iters = o.max_iters;
+    p.pricing = o.pricing;
     return p;
 }
 
@@ -544,6 +545,8 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     if (opts.placement < 0 || opts.placement > LP_PLACE_HBM)
         return fail(LP_ERR_ARG, "unknown placement %d", opts.placement);
     if (opts.scaling < 0 || opts.scaling > 64) return fail(LP_ERR_ARG, "scaling must lie in 0..64 (got %d)", opts.scaling);
+    if (opts.pricing != LP_PRICE_DANTZIG && opts.pricing != LP_PRICE_STEEPEST_EDGE)
+        return fail(LP_ERR_ARG, "unknown pricing %d", opts.pricing);
     if (num_lps == 0) return LP_OK;
     if (!A || !b || !c || !sense || !m || !n || !status || !x || !obj)
         return fail(LP_ERR_ARG, "a batch pointer is NULL");

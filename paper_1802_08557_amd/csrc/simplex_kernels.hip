@@ -176,11 +176,22 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
         T k1 = t_inf<T>();
         int k2 = BIG, p = -1;
         const T *obj = tab + (int64_t)m * ld;
+        const bool steep = prm.pricing == 1 && !bland;
         for (int j = tid; j < N; j += NT) {
             const T d = obj[j];
             const int bj = P.nonb[j];
             if (d > eps_opt && bj < nm) {
-                const T key = bland ? T(0) : -d;
+                T key = bland ? T(0) : -d;
+                if (steep) {
+                    // Steepest edge: d_j^2 / (1 + sum of column j's squares
+                    // over the live rows); threads walk down their columns.
+                    T w = T(1);
+                    for (int i = 0; i < m; ++i) {
+                        const T t = tab[(int64_t)i * ld + j];
+                        w = (P.rowf[i] & ROW_DEAD) ? w : fma(t, t, w);
+                    }
+                    key = -(d * d / w);
+                }
                 if (key < k1 || (key == k1 && bj < k2)) { k1 = key; k2 = bj; p = j; }
             }
         }

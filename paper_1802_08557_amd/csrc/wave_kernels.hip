@@ -201,7 +201,27 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
         if (P.iters >= P.cap) return kIterLimit;
         const bool bland = prm.k_deg > 0 && deg_run >= prm.k_deg;
         // Step 1.
-        const int e = price<T>(lane < N && P.d > eps_opt && P.nonb < nm, P.d, P.nonb, bland);
+        const bool elig = lane < N && P.d > eps_opt && P.nonb < nm;
+        int e;
+        if (prm.pricing == 1 && !bland) {
+            // Steepest edge: each eligible lane sums the squares of its own
+            // column over the live rows (contiguous in LDS).
+            const uint64_t dead0 = __ballot((P.rowf[0] & (kRowDead | kRowPad)) != 0);
+            const uint64_t dead1 = RB > 1 ? __ballot((P.rowf[RB - 1] & (kRowDead | kRowPad)) != 0) : 0;
+            T w = T(1);
+            if (elig) {
+                const T *col = tab + lane * ldm;
+#pragma unroll 4
+                for (int i = 0; i < m; ++i) {
+                    const T t = col[i];
+                    const uint64_t dm = i < 64 ? dead0 : dead1;
+                    w = ((dm >> (i & 63)) & 1) ? w : fma(t, t, w);
+                }
+            }
+            e = price<T>(elig, elig ? P.d * P.d / w : T(0), P.nonb, false);
+        } else {
+            e = price<T>(elig, P.d, P.nonb, bland);
+        }
         if (e < 0) return kOptimal;
         // Step 2: each lane's best row (ties to the smaller basic index), then
         // the wavefront minimum ratio, ties to the smallest basic index.

@@ -20,6 +20,7 @@ LP_LE, LP_GE, LP_EQ = 0, 1, 2
 OPTIMAL, INFEASIBLE, UNBOUNDED, ITERATION_LIMIT, NUMERICAL, INVALID_INPUT = range(6)
 PREC_FP64, PREC_FP32_CERT64 = 0, 1
 PLACE_AUTO, PLACE_LDS, PLACE_HBM = 0, 1, 2
+PRICE_DANTZIG, PRICE_STEEPEST_EDGE = 0, 1
 FLAG_SYNC, FLAG_TIME_KERNELS, FLAG_AUTOTUNE = 1, 2, 4
 STATS_WIDTH = 8
 LP_OK, LP_ERR_ARG, LP_ERR_NOMEM, LP_ERR_HIP = 0, -1, -2, -3
@@ -41,7 +42,7 @@ class LPOptions(ctypes.Structure):
                 ("stats", ctypes.c_void_p), ("stream", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("shared", ctypes.c_int32),
                 ("row_subset", ctypes.c_void_p), ("subset_m", ctypes.c_int32),
-                ("scaling", ctypes.c_int32)]
+                ("scaling", ctypes.c_int32), ("pricing", ctypes.c_int32)]
 
 
 class LPBatchError(RuntimeError):
@@ -192,10 +193,11 @@ class Context:
     def solve(self, batch: DeviceBatch, *, precision=PREC_FP64, max_iters=0, tol_piv=0.0,
               tol_opt=0.0, tol_feas=0.0, k_deg=50, placement=PLACE_AUTO, block_threads=0,
               stats=False, stream=None, sync=False, time_kernels=False, out=None,
-              row_subset=None, autotune=False, scaling=0) -> Solution:
+              row_subset=None, autotune=False, scaling=0, pricing=0) -> Solution:
         """Queue lp_batch_solve_ex on `stream` (default: torch's current stream).
         row_subset: int32 device tensor [N, subset_m] for a screened solve of a
-        shared batch.  scaling: passes of power-of-two scaling (0: off)."""
+        shared batch.  scaling: passes of power-of-two scaling (0: off).
+        pricing: PRICE_DANTZIG or PRICE_STEEPEST_EDGE."""
         import torch
         dev = batch.A.device
         N = batch.num_lps
@@ -219,6 +221,7 @@ class Context:
                    | (FLAG_AUTOTUNE if autotune else 0))
         o.shared = 1 if batch.shared else 0
         o.scaling = scaling
+        o.pricing = pricing
         if row_subset is not None:
             if row_subset.dim() != 2 or row_subset.shape[0] != N:
                 raise ValueError("row_subset must be [num_lps, subset_m]")
@@ -261,7 +264,7 @@ class Context:
         return A2, b2, c2, rexp, cexp
 
     def solve_host(self, A, b, c, sense, m, n, *, precision=PREC_FP64, chunk_lps=0, out=None,
-                   time_kernels=False, scaling=0):
+                   time_kernels=False, scaling=0, pricing=0):
         """lp_batch_solve_host on a batch in host memory: A, b, c, sense are
         numpy arrays or CPU torch tensors (pinned tensors are copied directly,
         pageable memory is staged by the library); m, n numpy int32.  Returns
@@ -290,6 +293,7 @@ class Context:
         self.lib.lp_options_init(ctypes.byref(o))
         o.precision = precision
         o.scaling = scaling
+        o.pricing = pricing
         o.flags = FLAG_TIME_KERNELS if time_kernels else 0
         _check(self.lib.lp_batch_solve_host(
             self.handle, N, host_ptr(A, "float64", cells, "A"), host_ptr(b, "float64", rows, "b"),
