@@ -288,6 +288,28 @@ def host_pipeline_block(batch, ctx, reps=3):
     return res
 
 
+def pricing_block(ctx, db, reps=5):
+    """Optional steepest-edge pricing on the benchmark batch, FP64: ms per
+    solve, LPs/s and pivots per LP, beside the same for Dantzig's rule (the
+    paper's, and the headline value's)."""
+    import torch
+    from paper_1802_08557_amd.lpbatch import PRICE_DANTZIG, PRICE_STEEPEST_EDGE
+    res = {}
+    for name, pr in (("dantzig", PRICE_DANTZIG), ("steepest_edge", PRICE_STEEPEST_EDGE)):
+        sol = ctx.solve(db, pricing=pr, stats=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sol = ctx.solve(db, pricing=pr, stats=True)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        st = sol.stats.cpu().numpy()
+        res[name] = dict(ms=t * 1e3, lps_per_s=db.num_lps / t,
+                         pivots_per_lp=float((st[:, 0].astype(np.int64) + st[:, 1]).mean()))
+    res["note"] = "optional pricing rule (default Dantzig); parity is checked in the tests"
+    return res
+
+
 def scaling_block(ctx, passes=4, reps=3, spread=3.0):
     """Optional scaling on a badly scaled copy of the benchmark batch (every
     row and column of every LP times 10^U[-spread, spread]; same optima): the
@@ -358,6 +380,7 @@ def main():
     ap.add_argument("--warm-sample", type=int, default=20_000)
     ap.add_argument("--no-host", action="store_true", help="skip the host-resident pipeline leg")
     ap.add_argument("--no-scaling", action="store_true", help="skip the scaling comparison")
+    ap.add_argument("--no-pricing", action="store_true", help="skip the steepest-edge comparison")
     ap.add_argument("--scaling-only", action="store_true", help="print only the scaling comparison")
     args = ap.parse_args()
     if args.copy_calibration > 0:
@@ -490,6 +513,11 @@ def main():
             rec["host_pipeline"] = host_pipeline_block(batch, ctx)
         except Exception as e:  # the main measurement stands on its own
             rec["host_pipeline"] = dict(error=f"{type(e).__name__}: {e}")
+    if not args.no_pricing and not args.graph and args.precision == "fp64":
+        try:
+            rec["pricing"] = pricing_block(ctx, db)
+        except Exception as e:  # the main measurement stands on its own
+            rec["pricing"] = dict(error=f"{type(e).__name__}: {e}")
     if not args.no_scaling and not args.graph and args.config == 1:
         try:
             rec["lp_scaling"] = scaling_block(ctx)
