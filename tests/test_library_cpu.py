@@ -45,7 +45,7 @@ def test_options_defaults(lib):
     o.precision = 7
     lib.lp_options_init(ctypes.byref(o))
     assert o.precision == 0 and o.k_deg == 50 and o.max_iters == 0 and o.flags == 0
-    assert o.stats is None and o.stream is None and o.scaling == 0
+    assert o.stats is None and o.stream is None and o.scaling == 0 and o.pricing == 0
 
 
 def test_options_layout_matches_the_header(tmp_path):
