@@ -96,3 +96,33 @@ def test_pivot_counts_and_argument_errors(ctx):
     with pytest.raises(lpbatch.LPBatchError) as ei:
         solve(ctx, bt, pricing=2)
     assert ei.value.code == lpbatch.LP_ERR_ARG
+
+
+def test_steepest_edge_in_screened_and_host_solves(ctx):
+    # Screened support-function solves (random 30-row relaxations, FP32, then
+    # the FP64 certificate, repair and re-solve, all with the same rule) and
+    # the host pipeline: every result equals the oracle's on the full LP.
+    import torch
+    from paper_1802_08557_amd.lpbatch import DeviceBatch
+    N = 800
+    P = W.polytope()
+    A1, b1 = W.split_form(P)
+    dirs = W.directions(N, seed=76)
+    c = np.concatenate([dirs, -dirs], axis=1)
+    m1, n1 = A1.shape
+    bt = W.Batch(np.tile(A1.reshape(-1), N), np.tile(b1, N), c.reshape(-1), np.zeros(N * m1, np.int8),
+                 np.full(N, m1, np.int32), np.full(N, n1, np.int32), "support_se")
+    ref = oracle_solve(bt, pricing=SE)
+    rng = np.random.default_rng(77)
+    sub = np.stack([rng.permutation(m1)[:30] for _ in range(N)]).astype(np.int32)
+    db = DeviceBatch.shared_from_host(A1, b1, np.zeros(m1, np.int8), c)
+    print("[gpu] screened solve with steepest edge", flush=True)
+    sol = ctx.solve(db, stats=True, precision=1, pricing=SE, row_subset=torch.from_numpy(sub).cuda())
+    torch.cuda.synchronize()
+    st, obj, x = sol.status.cpu().numpy(), sol.obj.cpu().numpy(), sol.x.cpu().numpy()
+    assert_parity(bt, st, obj, x, ref)
+    assert (sol.stats.cpu().numpy()[:, 3] > 0).any()  # some relaxations missed a tight row
+    ub = W.uneven_batch(100, seed=78, lo=3, hi=40)
+    print("[gpu] host solve with steepest edge", flush=True)
+    hst, hx, hobj = ctx.solve_host(ub.A, ub.b, ub.c, ub.sense, ub.m, ub.n, chunk_lps=30, pricing=SE)
+    assert_parity(ub, hst, hobj, hx, oracle_solve(ub, pricing=SE))
