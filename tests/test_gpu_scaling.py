@@ -166,3 +166,29 @@ def test_argument_errors(ctx):
         with pytest.raises(lpbatch.LPBatchError) as ei:
             gpu_scale(ctx, bt, bad)
         assert ei.value.code == lpbatch.LP_ERR_ARG
+
+
+def test_shared_and_screened_solves_with_scaling(ctx):
+    # Shared constraints: one scaled A, every c scaled by the same column
+    # factors, x mapped back per LP; with and without a screened first pass.
+    import torch
+    from paper_1802_08557_amd.lpbatch import DeviceBatch
+    N = 600
+    P = W.polytope()
+    A1, b1 = W.split_form(P)
+    rng = np.random.default_rng(67)
+    rf = 10.0 ** rng.uniform(-3, 3, size=A1.shape[0])
+    A1, b1 = A1 * rf[:, None], b1 * rf  # badly scaled rows, same polytope
+    dirs = W.directions(N, seed=68)
+    c = np.concatenate([dirs, -dirs], axis=1)
+    m1, n1 = A1.shape
+    bt = W.Batch(np.tile(A1.reshape(-1), N), np.tile(b1, N), c.reshape(-1), np.zeros(N * m1, np.int8),
+                 np.full(N, m1, np.int32), np.full(N, n1, np.int32), "support_rescaled_rows")
+    ref = solve_scaled(bt, PASSES, threads=8)
+    db = DeviceBatch.shared_from_host(A1, b1, np.zeros(m1, np.int8), c)
+    sub = torch.from_numpy(np.stack([rng.permutation(m1)[:48] for _ in range(N)]).astype(np.int32)).cuda()
+    for kw in (dict(precision=0), dict(precision=1, row_subset=sub)):
+        print(f"[gpu] shared solve with scaling {list(kw)}", flush=True)
+        sol = ctx.solve(db, stats=True, scaling=PASSES, **kw)
+        torch.cuda.synchronize()
+        assert_parity(bt, sol.status.cpu().numpy(), sol.obj.cpu().numpy(), sol.x.cpu().numpy(), ref)
