@@ -208,16 +208,29 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
             // column over the live rows (contiguous in LDS).
             const uint64_t dead0 = __ballot((P.rowf[0] & (kRowDead | kRowPad)) != 0);
             const uint64_t dead1 = RB > 1 ? __ballot((P.rowf[RB - 1] & (kRowDead | kRowPad)) != 0) : 0;
-            T w = T(1);
+            // 16-byte vectors down the column (padding rows past m are
+            // masked like dead ones), one partial sum per vector component.
+            using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+            constexpr int R = 16 / int(sizeof(T));
+            T acc[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = T(0);
             if (elig) {
-                const T *col = tab + lane * ldm;
-#pragma unroll 4
-                for (int i = 0; i < m; ++i) {
-                    const T t = col[i];
-                    const uint64_t dm = i < 64 ? dead0 : dead1;
-                    w = ((dm >> (i & 63)) & 1) ? w : fma(t, t, w);
+                const V *col = reinterpret_cast<const V *>(tab + lane * ldm);
+#pragma unroll 2
+                for (int i0 = 0; i0 < m; i0 += R) {
+                    const V t = col[i0 / R];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const int i = i0 + q;
+                        const uint64_t dm = i < 64 ? dead0 : dead1;
+                        acc[q] = ((dm >> (i & 63)) & 1) ? acc[q] : fma(t[q], t[q], acc[q]);
+                    }
                 }
             }
+            T w = T(1);
+#pragma unroll
+            for (int q = 0; q < R; ++q) w += acc[q];
             e = price<T>(elig, elig ? P.d * P.d / w : T(0), P.nonb, false);
         } else {
             e = price<T>(elig, P.d, P.nonb, bland);
