@@ -83,3 +83,17 @@ def test_without_gpu_context_creation_fails_cleanly(lib):
     assert rc in (lpbatch.LP_ERR_HIP, lpbatch.LP_ERR_ARG)
     assert not h.value
     assert lpbatch.last_error() != ""
+
+
+def test_header_enums_match_the_binding():
+    # The binding's copies of the header's enum values (precision, placement,
+    # pricing) and of the stats layout.
+    from paper_1802_08557_amd import lpbatch
+    text = open(HEADER).read()
+    val = lambda name: int(re.search(r"\b" + name + r"\s*=\s*(-?\d+)", text).group(1))
+    assert (lpbatch.PREC_FP64, lpbatch.PREC_FP32_CERT64) == (val("LP_PREC_FP64"), val("LP_PREC_FP32_CERT64"))
+    assert (lpbatch.PRICE_DANTZIG, lpbatch.PRICE_STEEPEST_EDGE) == (val("LP_PRICE_DANTZIG"),
+                                                                    val("LP_PRICE_STEEPEST_EDGE"))
+    width = int(re.search(r"#define LP_STATS_WIDTH (\d+)", text).group(1))
+    assert lpbatch.STATS_WIDTH == width
+
