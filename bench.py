@@ -21,10 +21,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X figures: 256 CUs at 2.4 GHz; HBM3E 8 TB/s; LDS 128 B/clk per CU.
+# MI355X published figures: 256 CUs at 2.4 GHz; HBM3E 8 TB/s.  LDS: 128 B/clk
+# per CU is the CDNA3-class figure (78.6 TB/s); the denominator of the LDS
+# roofline is the larger of it and the rates measured on the device itself
+# (lp_measure_peaks: 16-byte reads, and 16-byte read-then-write as in the
+# pivot sweep), so a higher CDNA4 rate is never missed.
 N_CU, CLOCK_HZ = 256, 2.4e9
 PEAK_HBM = 8.0e12
-PEAK_LDS = N_CU * 128 * CLOCK_HZ  # 78.6 TB/s
+LDS_NOMINAL = N_CU * 128 * CLOCK_HZ  # 78.6 TB/s
 
 METRIC = "LPs/sec at batch 1e5 (50x50 FP64, warm-start vs plain); % LDS/HBM roofline"
 
@@ -44,37 +48,90 @@ def workload(cfg):
     raise SystemExit(f"unknown config {cfg}")
 
 
+def surplus_columns(batch):
+    """Per LP, the rows that are >= after sign normalisation (rows with b < 0
+    are negated, flipping <= and >=): each adds a surplus column."""
+    neg = batch.b < 0
+    ge = ((batch.sense == 1) & ~neg) | ((batch.sense == 0) & neg)
+    roff = batch.offsets()[1]
+    return np.add.reduceat(ge.astype(np.int64), roff[:-1]) if batch.num_lps else np.zeros(0, np.int64)
+
+
 def algorithmic_bytes(batch, stats, tsize):
-    """Per-launch algorithmic bytes, split by where each LP's tableau lived.
-    Tableau: s*(m+1)*(N+1) to build the condensed tableau plus, per pivot, one
-    read and one write of it, 2*s*(m+1)*(N+1) (N = n non-basic columns for
-    all-<= rows) -- LDS traffic for LDS-resident tableaux (placement 1 or 3),
-    HBM traffic for tableaux in device-memory slots (placement 2).  HBM also
-    carries the inputs A, b, c, sense read once and x, obj, status, stats
-    written once.  Returns (lds_bytes, hbm_bytes, io_bytes, mean pivots)."""
+    """Per-launch algorithmic bytes, split by where each LP's tableau lived
+    (stats column 6).  N = n + surplus columns non-basic columns.
+      * one wavefront per LP (placement 1): the m x N constraint block lives in
+        LDS (the objective row and the right-hand sides stay in registers):
+        s*m*N written by the build, then read and written once per pivot;
+      * workgroup kernel, tableau in LDS (3) or in a device-memory slot (2): the
+        whole (m+1) x (N+1) condensed tableau, built once, read and written once
+        per pivot -- LDS traffic for 3, HBM traffic for 2.
+    HBM also carries the inputs A, b, c, sense read once and x, obj, status,
+    stats written once.  Returns (lds_bytes, hbm_bytes, io_bytes, mean pivots)."""
     m = batch.m.astype(np.float64)
     n = batch.n.astype(np.float64)
+    N = n + surplus_columns(batch)
     pivots = stats[:, 0].astype(np.float64) + stats[:, 1]
-    cells = (m + 1) * (n + 1)
+    place = stats[:, 6]
+    cells = np.where(place == 1, m * N, (m + 1) * (N + 1))
     tab = tsize * cells * (1.0 + 2.0 * pivots)
-    in_hbm = stats[:, 6] == 2
+    in_hbm = place == 2
     io = float(np.sum(8 * (m * n + m + n) + m + 8 * n + 8 + 4 + 4 * 8))
     return float(tab[~in_hbm].sum()), float(tab[in_hbm].sum()) + io, io, float(pivots.mean())
 
 
-def cpu_baseline(batch, max_lps=100_000):
+def roofline(per_kernel, dom, lds_bytes, hbm_bytes, peaks, workload_name):
+    """Roofline of the dominant solve kernel: the busier memory tier for the
+    algorithmic bytes, T = max(LDS bytes / LDS peak, HBM bytes / HBM peak),
+    against the kernel's measured time per solve.  The LDS peak is the larger
+    of the nominal 128 B/clk/CU and the device's measured rates; frac is also
+    given against the nominal figure alone."""
+    lds_peak = max([LDS_NOMINAL] + [peaks.get(k, 0.0) for k in ("lds_read", "lds_read_write")])
+    dom_s = per_kernel[dom] * 1e-3
+    if lds_bytes / lds_peak >= hbm_bytes / PEAK_HBM:
+        roof = dict(bound="lds", achieved=lds_bytes / dom_s / 1e9, peak=lds_peak / 1e9, unit="GB/s",
+                    frac=lds_bytes / dom_s / lds_peak)
+    else:
+        roof = dict(bound="hbm", achieved=hbm_bytes / dom_s / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                    frac=hbm_bytes / dom_s / PEAK_HBM)
+    tr = measured_traffic(dom, workload_name)
+    roof["traffic"] = tr["hbm"] if tr else None
+    roof.update(kernel=dom, kernel_ms=per_kernel[dom], lds_bytes_alg=lds_bytes, hbm_bytes_alg=hbm_bytes,
+                lds_frac=lds_bytes / dom_s / lds_peak, lds_frac_vs_nominal=lds_bytes / dom_s / LDS_NOMINAL,
+                hbm_frac=hbm_bytes / dom_s / PEAK_HBM,
+                lds_traffic=tr["lds"] if tr else None)
+    return roof
+
+
+def cpu_baseline(batch, max_lps=100_000, one_thread_lps=20_000):
+    """The oracle (plain C, FP64 full tableau, built with -march=native for
+    this host) on the first max_lps LPs of the benchmarked batch with one
+    thread per host core, and on the first one_thread_lps LPs with one thread."""
     import oracle
     k = min(batch.num_lps, max_lps)
     sample = batch.subset(np.arange(k)) if k < batch.num_lps else batch
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    oracle._load()
+    oracle.build(force=True, native=True)
+    oracle._load(native=True)
     t0 = time.perf_counter()
     res = oracle.solve(sample.A, sample.b, sample.c, sample.sense, sample.m, sample.n,
-                       threads=threads)
+                       threads=threads, native=True)
     dt = time.perf_counter() - t0
+    k1 = min(batch.num_lps, one_thread_lps)
+    s1 = batch.subset(np.arange(k1))
+    t1 = time.perf_counter()
+    oracle.solve(s1.A, s1.b, s1.c, s1.sense, s1.m, s1.n, threads=1, native=True)
+    dt1 = time.perf_counter() - t1
+    cpu = ""
+    try:
+        cpu = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return res, dict(value=k / dt, unit="LPs/s", cores=int(threads), kind="oracle",
-                     sample=f"first {k} LPs of the benchmarked batch, FP64 full-tableau oracle, "
-                            f"{threads} threads, {dt:.2f} s wall")
+                     sample=f"first {k} LPs of the benchmarked batch, FP64 full-tableau oracle "
+                            f"(gcc -O3 -march=native), {threads} threads, {dt:.2f} s wall",
+                     one_thread=dict(value=k1 / dt1, unit="LPs/s", sample=f"first {k1} LPs, {dt1:.2f} s"),
+                     cpu_model=cpu)
 
 
 KERNEL_SOURCES = ("paper_1802_08557_amd/csrc/wave_kernels.hip",
@@ -92,10 +149,13 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (profiles/traffic.json), scaled
-    by the factors the same counters read for a copy of known size; None when
-    the kernel sources changed since the counters were taken."""
+    """Bytes per launch of `kernel` on `workload` from the committed rocprofv3
+    counter summary (profiles/traffic.json): HBM from FETCH_SIZE + WRITE_SIZE
+    and LDS from SQ_INSTS_LDS_LOAD_BANDWIDTH + SQ_INSTS_LDS_STORE_BANDWIDTH,
+    each scaled by what the same counters read for kernels that move a known
+    number of bytes (a device copy; the LDS peak kernels).  None when the
+    kernel sources changed since the counters were taken; a missing figure is
+    None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -105,7 +165,9 @@ def measured_traffic(kernel, workload):
     ent = rec.get("kernels", {}).get(f"{kernel}@{workload}")
     if not ent:
         return None
-    return ent["fetch_bytes"] + ent["write_bytes"]
+    hbm = ent["fetch_bytes"] + ent["write_bytes"] if "fetch_bytes" in ent and "write_bytes" in ent else None
+    lds = ent["lds_load_bytes"] + ent["lds_store_bytes"] if "lds_load_bytes" in ent else None
+    return dict(hbm=hbm, lds=lds)
 
 
 def copy_calibration(gib):
@@ -354,6 +416,82 @@ def scaling_block(ctx, passes=4, reps=3, spread=3.0):
     return res
 
 
+def timed_solves(ctx, db, reps, warmup=1, **kw):
+    """reps solves of db timed with events on torch's current stream after
+    `warmup` untimed ones; per-kernel times from the library's own events over
+    the same solves.  Returns (ms per solve, {kernel: ms per solve},
+    {kernel: launches per solve}, last Solution)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = ctx.solve(db, stats=True, stream=stream, **kw)
+    kw.pop("autotune", None)
+    for _ in range(warmup):
+        ctx.solve(db, stats=True, stream=stream, out=out, **kw)
+    torch.cuda.synchronize()
+    ctx.kernel_times()
+    st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.record(stream)
+    for _ in range(reps):
+        ctx.solve(db, stats=True, stream=stream, out=out, time_kernels=True, **kw)
+    sp.record(stream)
+    torch.cuda.synchronize()
+    per, cnt = {}, {}
+    for nm, v in ctx.kernel_times():
+        per[nm] = per.get(nm, 0.0) + v / reps
+        cnt[nm] = cnt.get(nm, 0) + 1
+    return st.elapsed_time(sp) / reps, per, {k: v // reps for k, v in cnt.items()}, out
+
+
+def leg_record(batch, ms, per, launches, out, peaks, prec_name):
+    """One timed configuration: LPs/s, kernel times, the dominant solve
+    kernel's roofline and the certificate's outcome."""
+    stats = out.stats.cpu().numpy()
+    solve_kernels = {k: v for k, v in per.items() if k.startswith("simplex_") and "resolve" not in k}
+    dom = max(solve_kernels, key=solve_kernels.get)
+    lds_b, hbm_b, io_b, piv = algorithmic_bytes(batch, stats, 4 if prec_name == "fp32c" else 8)
+    roof = roofline(per, dom, lds_b, hbm_b, peaks, batch.name)
+    roof.update(launches_per_solve=launches[dom], mean_pivots=piv,
+                placement_counts={str(p): int(np.sum(stats[:, 6] == p)) for p in (1, 2, 3)})
+    rec = dict(precision=prec_name, ms=ms, lps_per_s=batch.num_lps / (ms * 1e-3),
+               kernels_ms={k: round(v, 4) for k, v in per.items()},
+               launches={k: v for k, v in launches.items()}, roofline=roof)
+    if prec_name == "fp32c":
+        rec.update(certified=int(np.sum((stats[:, 5] & 3) == 3) + np.sum((stats[:, 5] & 4) != 0)),
+                   fp64_resolves=int(np.sum(stats[:, 3] >= 1)),
+                   resolved_from_fp32_basis=int(np.sum(stats[:, 3] == 2)))
+    return rec
+
+
+def precision_block(ctx, db, batch, peaks, fp64_ms, reps=10):
+    """The benchmark batch on the FP32 tableau with the FP64 certificate of
+    every final basis (and the FP64 re-solve of those it rejects), beside the
+    FP64 solve of the headline: time, kernel split and the speed ratio."""
+    from paper_1802_08557_amd.lpbatch import PREC_FP32_CERT64
+    ms, per, launches, out = timed_solves(ctx, db, reps, warmup=2, precision=PREC_FP32_CERT64)
+    rec = leg_record(batch, ms, per, launches, out, peaks, "fp32c")
+    rec.update(workload=batch.name, fp64_ms=fp64_ms, speed_vs_fp64=fp64_ms / ms)
+    return rec
+
+
+def config_block(ctx, cfg, peaks, reps=3, autotune=False):
+    """Another configuration (500 x 500 tableaux streamed from device memory, or
+    the uneven 10..300 batch in autotuned size bins), FP64 and FP32 +
+    certificate: time per solve, LPs/s and the dominant solve kernel's roofline.
+    Parity at these sizes is checked LP by LP in the tests."""
+    from paper_1802_08557_amd.lpbatch import DeviceBatch, PREC_FP32_CERT64, PREC_FP64
+    batch = workload(cfg)
+    db = DeviceBatch.from_host(batch)
+    res = dict(workload=batch.name, num_lps=batch.num_lps)
+    for name, prec in (("fp64", PREC_FP64), ("fp32c", PREC_FP32_CERT64)):
+        ms, per, launches, out = timed_solves(ctx, db, reps, warmup=1, precision=prec, autotune=autotune)
+        res[name] = leg_record(batch, ms, per, launches, out, peaks, name)
+    res["fp32c_speed_vs_fp64"] = res["fp64"]["ms"] / res["fp32c"]["ms"]
+    if autotune:
+        res["tuning"] = [dict(bin=b, fp32=f, threads=t, hbm=h) for b, f, t, h in ctx.tuning()]
+    del db
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,6 +520,12 @@ def main():
     ap.add_argument("--no-scaling", action="store_true", help="skip the scaling comparison")
     ap.add_argument("--no-pricing", action="store_true", help="skip the steepest-edge comparison")
     ap.add_argument("--scaling-only", action="store_true", help="print only the scaling comparison")
+    ap.add_argument("--peaks", action="store_true",
+                    help="print only the measured LDS / HBM bandwidths (lp_measure_peaks)")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the peak measurement (the LDS roofline then uses the nominal figure)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the FP32 + certificate, uneven 10..300 and 500 x 500 legs")
     args = ap.parse_args()
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
@@ -403,10 +547,20 @@ def main():
         ctx.close()
         return 0
 
+    if args.peaks:
+        ctx = lpbatch.Context(0)
+        pk = ctx.measure_peaks()
+        pk.update({f"{k}_bytes_per_clk_per_cu": pk[k] / pk["num_cu"] / pk["clock_hz"]
+                   for k in ("lds_read", "lds_write", "lds_read_write", "lds_broadcast") if pk["clock_hz"] > 0})
+        print(json.dumps(pk), flush=True)
+        ctx.close()
+        return 0
+
     batch = workload(args.config)
     db = DeviceBatch.from_host(batch)
     ctx = lpbatch.Context(0)
     stream = torch.cuda.current_stream()
+    peaks = {} if args.no_peaks else ctx.measure_peaks()
     N = batch.num_lps
     prec = lpbatch.PREC_FP64 if args.precision == "fp64" else lpbatch.PREC_FP32_CERT64
     # allocates outputs once (and tunes the size bins when asked)
@@ -469,22 +623,8 @@ def main():
     obj = out.obj.cpu().numpy()
     lds_bytes, hbm_bytes, io_bytes, mean_piv = algorithmic_bytes(
         batch, stats, 8 if args.precision == "fp64" else 4)
-    # Roofline of the solve kernels: the time the busier memory tier needs for
-    # the algorithmic bytes, T = max(LDS bytes / LDS peak, HBM bytes / HBM peak),
-    # against the measured time of the dominant kernel.
-    dom_s = per_kernel[dom] * 1e-3
-    t_lds, t_hbm = lds_bytes / PEAK_LDS, hbm_bytes / PEAK_HBM
-    if t_lds >= t_hbm:
-        roof = dict(bound="lds", achieved=lds_bytes / dom_s / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s",
-                    frac=lds_bytes / dom_s / PEAK_LDS, traffic=None)
-    else:
-        roof = dict(bound="hbm", achieved=hbm_bytes / dom_s / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                    frac=hbm_bytes / dom_s / PEAK_HBM, traffic=None)
-    roof["traffic"] = measured_traffic(dom, batch.name)
-    roof.update(kernel=dom, kernel_ms=per_kernel[dom], launches_per_solve=launches[dom],
-                lds_bytes_alg=lds_bytes, hbm_bytes_alg=hbm_bytes,
-                io_bytes_alg=io_bytes, lds_frac=lds_bytes / dom_s / PEAK_LDS,
-                hbm_frac=hbm_bytes / dom_s / PEAK_HBM, mean_pivots=mean_piv,
+    roof = roofline(per_kernel, dom, lds_bytes, hbm_bytes, peaks, batch.name)
+    roof.update(launches_per_solve=launches[dom], io_bytes_alg=io_bytes, mean_pivots=mean_piv,
                 placement_counts={str(p): int(np.sum(stats[:, 6] == p)) for p in (1, 2, 3)})
     lds_resident = bool(np.all(stats[:, 6] != 2))
 
@@ -497,7 +637,8 @@ def main():
                            n=int(batch.n.max()), precision=args.precision,
                            seed=batch.meta.get("seed"), placement="lds" if lds_resident else "hbm"),
                roofline=roof, kernels_ms=per_kernel, wall_s=t_wall,
-               launch="hip_graph_replay" if graph is not None else "eager")
+               launch="hip_graph_replay" if graph is not None else "eager",
+               peaks=peaks or None)
     if args.autotune:
         rec["tuning"] = [dict(bin=b, fp32=f, threads=t, hbm=h) for b, f, t, h in ctx.tuning()]
     if not args.no_cpu:
@@ -528,6 +669,14 @@ def main():
             rec["warm_start"] = warm_start_block(args)
         except Exception as e:  # the main measurement stands on its own
             rec["warm_start"] = dict(error=f"{type(e).__name__}: {e}")
+    if not args.no_legs and not args.graph and args.config == 1 and args.precision == "fp64":
+        for key, fn in (("fp32_certified", lambda: precision_block(ctx, db, batch, peaks, ms_per_step)),
+                        ("large_500x500", lambda: config_block(ctx, 4, peaks)),
+                        ("uneven_10_300", lambda: config_block(ctx, 2, peaks, autotune=True))):
+            try:
+                rec[key] = fn()
+            except Exception as e:  # the main measurement stands on its own
+                rec[key] = dict(error=f"{type(e).__name__}: {e}")
     if args.precision == "fp32c":
         rec["certificate"] = dict(certified=int(np.sum((stats[:, 5] & 3) == 3) + np.sum((stats[:, 5] & 4) != 0)),
                                   resolved_fp64=int(np.sum(stats[:, 3] >= 1)))

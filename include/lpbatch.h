@@ -350,6 +350,37 @@ int lp_mlp_train_step(lp_ctx *ctx, int64_t B, const float *dirs, const uint8_t *
 int lp_mlp_save(lp_ctx *ctx, const char *path);
 int lp_mlp_load(lp_ctx *ctx, const char *path);
 
+/*
+ * lp_measure_peaks -- measured bandwidth of the memory tiers the solve kernels
+ * are priced against.  A pivot (paper Sec. 4.1, Step 3, and its
+ * implementation discussion around Listing 1) is a rank-1 update -- one fma
+ * per tableau element against one read and one write of it -- so a solve is
+ * bound by the bandwidth of wherever its tableau lives: LDS for tableaux
+ * resident on a CU, device memory (HBM) for streamed ones.  Each figure is the
+ * best of three timed launches on the context's device, in bytes per second:
+ *   lds_read        16-byte reads, each wavefront reading 1 KB of consecutive
+ *                   LDS addresses per instruction (bank-conflict free);
+ *   lds_write       the same pattern written;
+ *   lds_read_write  each 16-byte slot read and then written back, bytes read
+ *                   plus bytes written (the pattern of the pivot's row sweep);
+ *   lds_broadcast   bytes delivered to lanes when every lane of a wavefront
+ *                   reads the same 16 bytes (the pivot column's values);
+ *   hbm_copy        bytes read plus bytes written by a 16-byte-vector copy of
+ *                   1 GiB in device memory;
+ * clock_hz is the shader clock during the LDS read run (its clock counter
+ * against the constant 100 MHz reference counter), num_cu the CU count.  The
+ * LDS runs use sixteen wavefronts per CU.  Synchronous; allocates and frees
+ * about 2 GiB of device memory.  Returns LP_OK, LP_ERR_ARG (NULL argument) or
+ * LP_ERR_HIP.
+ */
+typedef struct {
+    double lds_read, lds_write, lds_read_write, lds_broadcast, hbm_copy;
+    double clock_hz;
+    int32_t num_cu;
+} lp_peaks;
+
+int lp_measure_peaks(lp_ctx *ctx, lp_peaks *out);
+
 /* Text of the last failure on the calling thread ("" if none). */
 const char *lp_last_error(void);
 

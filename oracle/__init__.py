@@ -25,21 +25,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "simplex_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
 
 OPTIMAL, INFEASIBLE, UNBOUNDED, ITERATION_LIMIT, NUMERICAL, INVALID_INPUT = range(6)
 LE, GE, EQ = 0, 1, 2
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, native: bool = False) -> str:
     """Compile the C oracle into ``oracle/liboracle.so`` (portable x86-64, no
-    fast-math, no FP contraction: each operation rounds once, as written)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+    fast-math, no FP contraction: each operation rounds once, as written).
+    native=True builds ``liboracle_native.so`` with ``-march=native`` for the
+    host it runs on (the CPU-baseline timing); without contraction or
+    fast-math its results are the same bits."""
+    lib = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O3", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+            ["gcc", "-O3"] + (["-march=native"] if native else []) +
+            ["-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
              "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm", "-lpthread"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Params(ctypes.Structure):
@@ -48,19 +54,17 @@ class _Params(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("pricing", ctypes.c_int32)]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        build(force=False)
-        lib = ctypes.CDLL(_LIB)
+def _load(native: bool = False):
+    if native not in _libs:
+        lib = ctypes.CDLL(build(force=False, native=native))
         lib.oracle_solve_batch.restype = ctypes.c_int
         lib.oracle_solve_batch.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 6 + [
             ctypes.POINTER(_Params), ctypes.c_int] + [ctypes.c_void_p] * 5
-        _lib = lib
-    return _lib
+        _libs[native] = lib
+    return _libs[native]
 
 
 @dataclass
@@ -78,11 +82,12 @@ def _p(a, dt):
 
 
 def solve(A, b, c, sense, m, n, *, tol_piv=1e-9, tol_opt=1e-9, tol_feas=1e-9,
-          k_deg=50, max_iters=0, threads=1, pricing=0) -> Result:
+          k_deg=50, max_iters=0, threads=1, pricing=0, native=False) -> Result:
     """Solve a batch of LPs (max c^T x, A x {<=,>=,=} b, x >= 0) stored back to
     back: A row-major per LP, b/sense per row, c per column, m/n per LP.
-    pricing: 0 Dantzig (the paper's Step 1), 1 steepest edge."""
-    lib = _load()
+    pricing: 0 Dantzig (the paper's Step 1), 1 steepest edge.  native: the
+    -march=native build (same results)."""
+    lib = _load(native)
     m_, pm = _p(np.atleast_1d(m), np.int32)
     n_, pn = _p(np.atleast_1d(n), np.int32)
     N = m_.shape[0]

@@ -230,8 +230,15 @@ __host__ __device__ inline LdsLayout lds_layout(int m, int ncol_max, int64_t tsi
     return L;
 }
 
-// Row stride of a tableau with C = (non-basic columns + 1) entries per row: odd,
-// so that walking a column of an LDS-resident tableau spreads over the banks.
-__host__ __device__ inline int tableau_ld(int C) { return C | 1; }
+// Row stride (elements) of a workgroup-kernel tableau with C = (non-basic
+// columns + 1) entries per row and tsize-byte entries: an odd number of
+// 16-byte units, so every row starts 16-byte aligned (the pivot sweep moves
+// 16 bytes per lane per access) and walking a column of an LDS-resident
+// tableau spreads over the banks.
+__host__ __device__ inline int tableau_ld(int C, int tsize)
+{
+    const int R = 16 / tsize;
+    return R * (((C + R - 1) / R) | 1);
+}
 
 }  // namespace lpb

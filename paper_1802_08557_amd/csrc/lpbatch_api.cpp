@@ -137,8 +137,8 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
     lpb::LdsLayout L = lpb::lds_layout(P.m_max, ncol_worst, ts, lpb::simplex_ctrl_bytes(fp32));
     // Tableau budget for the common case of no surplus columns (every row <= after
     // normalisation); LPs with more columns than budgeted move to HBM by themselves.
-    const int64_t tab_common = int64_t(P.m_max + 1) * lpb::tableau_ld(P.n_max + 1) * ts;
-    const int64_t tab_worst = int64_t(P.m_max + 1) * lpb::tableau_ld(ncol_worst + 1) * ts;
+    const int64_t tab_common = int64_t(P.m_max + 1) * lpb::tableau_ld(P.n_max + 1, int(ts)) * ts;
+    const int64_t tab_worst = int64_t(P.m_max + 1) * lpb::tableau_ld(ncol_worst + 1, int(ts)) * ts;
     const int64_t cells = int64_t(P.m_max + 1) * (P.n_max + 1);
     int nt = opts.block_threads;
     if (!nt) nt = cells <= 64 * 64 ? 64 : (cells <= 256 * 256 ? 256 : 512);
@@ -225,8 +225,8 @@ int launch_block(lp_ctx *ctx, bool fp32, lpb::SolveArgs a, const BinLaunch &B, c
     const int64_t ts = fp32 ? 4 : 8;
     const int ncol_worst = B.n_max + B.m_max;
     lpb::LdsLayout L = lpb::lds_layout(B.m_max, ncol_worst, ts, lpb::simplex_ctrl_bytes(fp32));
-    const int64_t tab_common = int64_t(B.m_max + 1) * lpb::tableau_ld(B.n_max + 1) * ts;
-    const int64_t tab_worst = int64_t(B.m_max + 1) * lpb::tableau_ld(ncol_worst + 1) * ts;
+    const int64_t tab_common = int64_t(B.m_max + 1) * lpb::tableau_ld(B.n_max + 1, int(ts)) * ts;
+    const int64_t tab_worst = int64_t(B.m_max + 1) * lpb::tableau_ld(ncol_worst + 1, int(ts)) * ts;
     int64_t lds = L.tab;
     const bool want_lds = !B.force_hbm && L.tab + tab_common <= lds_budget(ctx, B.placement);
     if (want_lds) lds = L.tab + tab_common;
@@ -801,10 +801,8 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             ca.kl = kl;
             ca.stage_a = stage;
             ca.lds_bytes = int32_t(lds);
-            if (screened) {
-                ca.viol = d_viol;
-                viol_counted = true;
-            }
+            ca.viol = d_viol;
+            viol_counted = true;
             const int per_cu = lpb::certify_wave_blocks_per_cu(W, int(lds));
             if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
             const int64_t cgrid = std::min<int64_t>((num_lps + W - 1) / W, int64_t(per_cu) * ctx->num_cu);
@@ -840,18 +838,17 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         a64.enter_out = nullptr;
         a64.refine_stats = 1;
         a64.row_subset = nullptr;
-        if (screened) {
-            // Start each re-solve from its relaxation's final basis and repair it
-            // with the dual simplex method (LPs it does not finish go on to a
-            // solve from the slack basis).
-            a64.warm_basis = d_basis;
-            a64.warm_rows = opts.row_subset;
-            a64.warm_m = opts.subset_m;
-            // A relaxation optimum that violates many rows is far from the
-            // LP's: the slack-basis solve is cheaper than the repair then.
-            a64.warm_viol = viol_counted ? d_viol : nullptr;
-            a64.warm_max_viol = 16;
-        }
+        // Start each re-solve from the single-precision solve's final basis --
+        // of the relaxation when screened, of the LP itself otherwise -- and
+        // repair it with the dual (or primal) simplex method; LPs the repair
+        // does not finish go on to a solve from the slack basis.
+        a64.warm_basis = d_basis;
+        a64.warm_rows = screened ? opts.row_subset : nullptr;
+        a64.warm_m = screened ? opts.subset_m : 0;
+        // A start whose x violates many rows is far from the LP's optimum: the
+        // slack-basis solve is cheaper than the repair then.
+        a64.warm_viol = viol_counted ? d_viol : nullptr;
+        a64.warm_max_viol = 16;
         if (P_full.uniform) a64.um = P_full.m0;
         int64_t n_wave64 = 0;
         int wm64 = 0, wn64 = 0;

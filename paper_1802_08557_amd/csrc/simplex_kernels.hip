@@ -51,7 +51,8 @@ template <typename T>
 struct Ctrl {
     int ng, nart, neq, bad;
     int next;
-    int pad[3];
+    int cnt;  // scratch tally (warm start)
+    int pad[2];
     double bnorm, cnorm;
     T rv[16];
     int ri[16];
@@ -139,15 +140,43 @@ __device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
     for (int i = tid; i <= m; i += NT)
         P.pcol[i] = (i < m && (P.rowf[i] & ROW_DEAD)) ? T(0) : tab[(int64_t)i * ld + e];
     __syncthreads();
+    // Sweep: each wavefront takes whole rows, every lane 16 bytes (R entries)
+    // per access and U accesses in flight -- all loads, then the fmas, then
+    // all stores.  Rows start 16-byte aligned (tableau_ld); the entries past C
+    // up to the row stride are padding, updated with whatever they hold and
+    // never read back (the pivot-row buffer is padded the same way).
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int R = 16 / int(sizeof(T));
+    constexpr int U = 4;
+    const int nv = (C + R - 1) / R;
+    const V *pr = reinterpret_cast<const V *>(P.prow);
     for (int i = wave; i <= m; i += W) {
-        T *row = tab + (int64_t)i * ld;
+        V *row = reinterpret_cast<V *>(tab + (int64_t)i * ld);
         if (i == l) {
-            for (int j = lane; j < C; j += 64) row[j] = P.prow[j];
-        } else {
-            const T f = P.pcol[i];
-            for (int j = lane; j < C; j += 64) {
-                const T base = (j == e) ? T(0) : row[j];
-                row[j] = fma(-f, P.prow[j], base);
+            for (int k = lane; k < nv; k += 64) row[k] = pr[k];
+            continue;
+        }
+        const T f = P.pcol[i];
+        for (int k0 = lane; k0 < nv; k0 += 64 * U) {
+            V v[U], w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 64 * u;
+                if (k < nv) { v[u] = row[k]; w[u] = pr[k]; }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 64 * u;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T base = (k * R + r == e) ? T(0) : v[u][r];
+                    v[u][r] = fma(-f, w[u][r], base);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 64 * u;
+                if (k < nv) row[k] = v[u];
             }
         }
     }
@@ -218,19 +247,16 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
     }
 }
 
-// Solve LP k with the tableau at P.tab (LDS or HBM).  Row classification
-// (rowf, colrow, Ctrl counts) has been done by the caller.
+// A1/A2: non-basic and basic index arrays, then the tableau rows
+// (sign-normalised so every rhs is >= 0, with a -1 surplus entry per >= row).
+// Returns whether this thread saw a non-finite entry of A or b.
 template <typename T, int NT>
-__device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int placement)
+__device__ __forceinline__ bool fill_tableau(LP<T, NT> &P)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int W = NT / 64;
     const int m = P.m, n = P.n, N = P.N, C = P.C, ld = P.ld;
-    Ctrl<T> *sh = P.sh;
     T *tab = P.tab;
-
-    // A1/A2: non-basic and basic index arrays, then the tableau rows
-    // (sign-normalised so every rhs is >= 0, with a -1 surplus entry per >= row).
     for (int j = tid; j < N; j += NT) P.nonb[j] = (j < n) ? j : n + P.colrow[j - n];
     for (int i = tid; i < m; i += NT)
         P.basis[i] = (row_sense(P.rowf[i]) == LE) ? n + i : n + m + i;
@@ -253,6 +279,163 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
             row[j] = T(v);
         }
     }
+    return bad;
+}
+
+// Phase II objective row: c priced out over the current basis, rows in order.
+template <typename T, int NT>
+__device__ __forceinline__ void price_out(LP<T, NT> &P)
+{
+    const int tid = threadIdx.x;
+    const int m = P.m, n = P.n, N = P.N, C = P.C, ld = P.ld;
+    T *tab = P.tab;
+    for (int i = tid; i < m; i += NT) {
+        const int bv = P.basis[i];
+        P.pcol[i] = ((P.rowf[i] & ROW_DEAD) || bv >= n) ? T(0) : T(P.c[bv]);
+    }
+    __syncthreads();
+    for (int j = tid; j < C; j += NT) {
+        const int bj = (j < N) ? P.nonb[j] : BIG;
+        T acc = (bj < n) ? T(P.c[bj]) : T(0);
+        for (int i = 0; i < m; ++i) {
+            const T cb = P.pcol[i];
+            if (cb != T(0)) acc = fma(-cb, tab[(int64_t)i * ld + j], acc);
+        }
+        tab[(int64_t)m * ld + j] = acc;
+    }
+    __syncthreads();
+}
+
+// Warm start of an FP64 re-solve from the final basis of the single-precision
+// solve of the same LP (basis at warm_basis + P.ro, LP numbering; all rows <=
+// after normalisation, so the tableau starts at the slack basis).  Tight rows
+// are those whose slack is non-basic in the start basis; every basic
+// structural enters, in row order, at the tight row of largest |entry| in its
+// column not yet used (ties to the lower row).  Returns false -- the tableau
+// then holds some mix and must be rebuilt -- when the start basis is not square
+// on its tight rows or a pivot entry falls below tol_piv.  P.colrow (unused
+// without surplus columns) holds the tight-row flags.
+template <typename T, int NT>
+__device__ bool crash(LP<T, NT> &P, const SolveArgs &a)
+{
+    const int tid = threadIdx.x;
+    const int m = P.m, n = P.n, N = P.N, ld = P.ld;
+    const T *tab = P.tab;
+    const int32_t *wb = a.warm_basis + P.ro;
+    Ctrl<T> *sh = P.sh;
+    int *tight = P.colrow;
+    for (int i = tid; i < m; i += NT) tight[i] = 1;
+    if (tid == 0) { sh->bad = 0; sh->cnt = 0; }
+    __syncthreads();
+    int cnt = 0;  // basic structurals minus tight rows, this thread's share
+    for (int r = tid; r < m; r += NT) {
+        const int v = wb[r];
+        if (v < 0 || v >= n + m) sh->bad = 1;  // not a basis of this all-<= LP
+        else if (v >= n) tight[v - n] = 0;     // basic slack: its row is not tight
+        else ++cnt;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) cnt -= tight[i];
+    if (cnt) atomicAdd(&sh->cnt, cnt);
+    __syncthreads();
+    if (sh->bad || sh->cnt != 0) return false;
+    const T tol_piv = T(a.prm.tol_piv);
+    for (int r = 0; r < m; ++r) {
+        const int v = wb[r];
+        if (v >= n) continue;
+        // The structural's column (it must still be non-basic).
+        T k1 = T(0);
+        int k2 = BIG, p = -1;
+        for (int j = tid; j < N; j += NT)
+            if (P.nonb[j] == v) { k2 = j; p = j; }
+        block_argmin<T, NT>(k1, k2, p, sh);
+        if (p < 0) return false;
+        const int c = p;
+        // The unused tight row of largest |entry| (ties to the lower row).
+        k1 = t_inf<T>(); k2 = BIG; p = -1;
+        for (int i = tid; i < m; i += NT) {
+            if (!tight[i]) continue;
+            const T t = -fabs(tab[(int64_t)i * ld + c]);
+            if (t < k1 || (t == k1 && i < k2)) { k1 = t; k2 = i; p = i; }
+        }
+        block_argmin<T, NT>(k1, k2, p, sh);
+        if (p < 0 || !(-k1 > tol_piv)) return false;
+        if (tid == 0) tight[p] = 0;
+        pivot<T, NT>(P, p, c);
+        ++P.iters;
+    }
+    return true;
+}
+
+// Repair of the crashed start (objective row priced out): the dual simplex
+// method, with d_j taken as min(d_j, 0), restores primal feasibility when the
+// start is dual feasible up to the single-precision level tol_dual -- leaving
+// row: the most negative right-hand side below -tol_p (ties to the smallest
+// basic Bland index); entering column: the smallest min(d_j, 0) / t_lj over
+// t_lj < -tol_piv (ties to the smallest Bland index) -- then the primal method
+// removes any d_j > eps_opt left.  A primal feasible start that is not dual
+// feasible goes straight to the primal method.  Returns the status, or -1
+// when the start is neither.
+template <typename T, int NT>
+__device__ int dual_repair(LP<T, NT> &P, T eps_opt, T tol_dual, T tol_p, const SolveParams &prm, int *enter)
+{
+    const int tid = threadIdx.x;
+    const int m = P.m, N = P.N, ld = P.ld, nm = P.n + P.m;
+    T *tab = P.tab;
+    const T tol_piv = T(prm.tol_piv);
+    Ctrl<T> *sh = P.sh;
+    // Dual and primal feasibility of the start.
+    double dmax = -1.0, pinf = -1.0;
+    for (int j = tid; j < N; j += NT)
+        if (P.nonb[j] < nm && tab[(int64_t)m * ld + j] > tol_dual) dmax = 1.0;
+    for (int i = tid; i < m; i += NT)
+        if (!(P.rowf[i] & ROW_DEAD) && tab[(int64_t)i * ld + N] < -tol_p) pinf = 1.0;
+    const bool dual_bad = block_max<T, NT>(dmax, sh) > 0.0;
+    const bool primal_bad = block_max<T, NT>(pinf, sh) > 0.0;
+    if (dual_bad) return primal_bad ? -1 : simplex<T, NT>(P, eps_opt, prm, enter);
+    for (;;) {
+        if (P.iters >= P.cap) return ST_ITER;
+        T k1 = t_inf<T>();
+        int k2 = BIG, p = -1;
+        for (int i = tid; i < m; i += NT) {
+            if (P.rowf[i] & ROW_DEAD) continue;
+            const T v = tab[(int64_t)i * ld + N];
+            const int bb = P.basis[i];
+            if (v < -tol_p && (v < k1 || (v == k1 && bb < k2))) { k1 = v; k2 = bb; p = i; }
+        }
+        block_argmin<T, NT>(k1, k2, p, sh);
+        if (p < 0) break;  // primal feasible
+        const int l = p;
+        k1 = t_inf<T>(); k2 = BIG; p = -1;
+        for (int j = tid; j < N; j += NT) {
+            const int bj = P.nonb[j];
+            const T t = tab[(int64_t)l * ld + j];
+            if (bj < nm && t < -tol_piv) {
+                const T d = tab[(int64_t)m * ld + j];
+                const T ratio = (d < T(0) ? d : T(0)) / t;
+                if (ratio < k1 || (ratio == k1 && bj < k2)) { k1 = ratio; k2 = bj; p = j; }
+            }
+        }
+        block_argmin<T, NT>(k1, k2, p, sh);
+        if (p < 0) return ST_INFEASIBLE;  // row l cannot reach its bound
+        pivot<T, NT>(P, l, p);
+        ++P.iters;
+    }
+    return simplex<T, NT>(P, eps_opt, prm, enter);
+}
+
+// Solve LP k with the tableau at P.tab (LDS or HBM).  Row classification
+// (rowf, colrow, Ctrl counts) has been done by the caller.
+template <typename T, int NT>
+__device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int placement)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int W = NT / 64;
+    const int m = P.m, n = P.n, N = P.N, C = P.C, ld = P.ld;
+    Ctrl<T> *sh = P.sh;
+    T *tab = P.tab;
+
+    bool bad = fill_tableau<T, NT>(P);
     double cmax = 0.0;
     for (int j = tid; j < n; j += NT) {
         const double cj = P.c[j];
@@ -271,6 +454,20 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
     P.cap = a.prm.max_iters > 0 ? a.prm.max_iters
                                 : 50 * (m + n + (m - sh->neq) + P.nart);
 
+    // Warm start of an FP64 re-solve from the single-precision solve's final
+    // basis of this LP (not for screened solves, whose repair the wavefront
+    // kernel does): only when that solve ended optimal -- its status is still
+    // in status[k] -- with few violated rows, and only for all-<= LPs.
+    bool warm = !invalid && a.warm_basis && !a.warm_rows && P.nart == 0 && a.status[P.k] == ST_OPTIMAL &&
+                !(a.warm_viol && a.warm_viol[P.k] > a.warm_max_viol);
+    if (warm && !crash<T, NT>(P, a)) {
+        // The crash stopped part-way: rebuild the slack-basis tableau.
+        warm = false;
+        __syncthreads();
+        fill_tableau<T, NT>(P);
+        P.iters = 0;
+        __syncthreads();
+    }
     if (invalid) {
         status = ST_INVALID;
     } else {
@@ -320,22 +517,25 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
         }
         if (status == ST_OPTIMAL) {
             // Phase II objective row: c priced out over the current basis.
-            for (int i = tid; i < m; i += NT) {
-                const int bv = P.basis[i];
-                P.pcol[i] = ((P.rowf[i] & ROW_DEAD) || bv >= n) ? T(0) : T(P.c[bv]);
-            }
-            __syncthreads();
-            for (int j = tid; j < C; j += NT) {
-                const int bj = (j < N) ? P.nonb[j] : BIG;
-                T acc = (bj < n) ? T(P.c[bj]) : T(0);
-                for (int i = 0; i < m; ++i) {
-                    const T cb = P.pcol[i];
-                    if (cb != T(0)) acc = fma(-cb, tab[(int64_t)i * ld + j], acc);
+            price_out<T, NT>(P);
+            const T eps_opt = T(a.prm.tol_opt * fmax(1.0, cnorm));
+            if (warm) {
+                // Single-precision level for the start's reduced costs.
+                status = dual_repair<T, NT>(P, eps_opt, T(1e-5 * fmax(1.0, cnorm)),
+                                            T(a.prm.tol_feas * (1.0 + bnorm)), a.prm, &enter);
+                if (status < 0) {
+                    // Neither primal nor dual feasible: solve from the slack basis.
+                    warm = false;
+                    __syncthreads();
+                    fill_tableau<T, NT>(P);
+                    P.iters = 0;
+                    __syncthreads();
+                    price_out<T, NT>(P);
+                    status = simplex<T, NT>(P, eps_opt, a.prm, &enter);
                 }
-                tab[(int64_t)m * ld + j] = acc;
+            } else {
+                status = simplex<T, NT>(P, eps_opt, a.prm, &enter);
             }
-            __syncthreads();
-            status = simplex<T, NT>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
         }
     }
 
@@ -380,7 +580,7 @@ __device__ __forceinline__ void solve_lp(LP<T, NT> &P, const SolveArgs &a, int p
             if (a.stats) {
                 int32_t *st = a.stats + 8 * P.k;
                 if (a.refine_stats) {
-                    st[3] = 1;
+                    st[3] = warm ? 2 : 1;  // 2: started from the single-precision basis
                     st[4] = P.iters;
                 } else {
                     st[0] = P.it1;
@@ -518,7 +718,7 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         __syncthreads();
         P.N = n + sh->ng;
         P.C = P.N + 1;
-        P.ld = tableau_ld(P.C);
+        P.ld = tableau_ld(P.C, int(sizeof(T)));
         P.nart = sh->nart;
         const int64_t tab_bytes = int64_t(m + 1) * P.ld * int64_t(sizeof(T));
         const bool in_lds = !a.force_hbm && L.tab + tab_bytes <= int64_t(a.lds_bytes);

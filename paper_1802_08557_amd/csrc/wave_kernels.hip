@@ -271,35 +271,39 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
     }
 }
 
-// Warm start from the final basis of a relaxation solved on a subset of the
-// rows (all rows <= after normalisation, so the tableau starts at the slack
-// basis).  The relaxation's basis holds its basic structurals and the slacks
-// of some of its rows; the other relaxation rows ("tight": slack non-basic)
-// must lose their slacks.  Crash: every basic structural enters, in
-// relaxation row order, at the tight row of largest |entry| in its column not
-// yet used; the full LP's basis then is the relaxation's plus the slacks of
-// the omitted rows.  Returns false when a pivot entry falls below tol_piv or
-// the relaxation basis is not square on its tight rows.
+// Warm start from a final basis of a single-precision solve: either of a
+// relaxation solved on a subset of the rows (warm_rows set: warm_m rows per
+// LP, its basis at warm_basis + k * warm_m in relaxation numbering) or of the
+// LP itself (warm_rows NULL: its basis at warm_basis + P.ro, LP numbering).
+// All rows are <= after normalisation, so the tableau starts at the slack
+// basis.  The start basis holds its basic structurals and the slacks of some
+// of its rows; the other rows ("tight": slack non-basic) must lose their
+// slacks.  Crash: every basic structural enters, in row order, at the tight
+// row of largest |entry| in its column not yet used; the full LP's basis then
+// is the start basis plus the slacks of any omitted rows.  Returns false when
+// a pivot entry falls below tol_piv or the start basis is not square on its
+// tight rows.
 template <typename T, int RB>
 __device__ bool crash(WaveLP<T, RB> &P, const SolveArgs &a, int64_t k)
 {
     const int lane = threadIdx.x;
-    const int wm = a.warm_m, n = P.n, m = P.m, ldm = P.ldm;
-    const int32_t *wb = a.warm_basis + k * int64_t(wm);
-    const int32_t *wr = a.warm_rows + k * int64_t(wm);
+    const int n = P.n, m = P.m, ldm = P.ldm;
+    const int wm = a.warm_rows ? a.warm_m : m;
+    const int32_t *wb = a.warm_rows ? a.warm_basis + k * int64_t(wm) : a.warm_basis + P.ro;
+    const int32_t *wr = a.warm_rows ? a.warm_rows + k * int64_t(wm) : nullptr;
     const T tol_piv = T(a.prm.tol_piv);
     uint64_t cand[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) cand[r] = 0;
     int nstruct = 0;
-    // Tight rows: the relaxation's rows, less those whose slack is basic.
+    // Tight rows: the start basis's rows, less those whose slack is basic.
     for (int r0 = 0; r0 < wm; r0 += 64) {
         const int r = r0 + lane;
         int q = -1, v = -1, qs = -1;
         if (r < wm) {
-            q = wr[r];
+            q = wr ? wr[r] : r;
             v = wb[r];
-            if (v >= n && v < n + wm) qs = wr[v - n];  // the row of a basic slack
+            if (v >= n && v < n + wm) qs = wr ? wr[v - n] : v - n;  // the row of a basic slack
         }
         nstruct += __popcll(__ballot(r < wm && v >= 0 && v < n));
         for (int pass = 0; pass < 2; ++pass) {
@@ -357,22 +361,32 @@ __device__ bool crash(WaveLP<T, RB> &P, const SolveArgs &a, int64_t k)
     return true;
 }
 
-// Repair of a start basis that is dual feasible up to the single-precision
-// level (the final basis of an FP32 relaxation) but may violate rows: the
-// dual simplex method, with d_j taken as min(d_j, 0), restores primal
-// feasibility -- the leaving row is the most negative right-hand side below
-// -tol_p (ties to the smallest basic Bland index), the entering column the
-// smallest min(d_j, 0) / t_lj over t_lj < -tol_piv (ties to the smallest Bland
-// index) -- and the primal method then removes any d_j > eps_opt left.
-// Returns the status, or -1 when the start is further from dual feasibility
-// than tol_dual (the caller then solves from the slack basis).
+// Repair of a start basis from a single-precision solve (the final basis of
+// an FP32 relaxation, or of the FP32 solve of the LP itself), which the FP64
+// arithmetic may find slightly primal or dual infeasible.  A start that is
+// dual feasible up to the single-precision level: the dual simplex method,
+// with d_j taken as min(d_j, 0), restores primal feasibility -- the leaving
+// row is the most negative right-hand side below -tol_p (ties to the smallest
+// basic Bland index), the entering column the smallest min(d_j, 0) / t_lj over
+// t_lj < -tol_piv (ties to the smallest Bland index) -- and the primal method
+// then removes any d_j > eps_opt left.  A start that is primal feasible but
+// not dual feasible goes straight to the primal method.  Returns the status,
+// or -1 when the start is neither (the caller then solves from the slack
+// basis).
 template <typename T, int RB>
 __device__ int dual_repair(WaveLP<T, RB> &P, T eps_opt, T tol_dual, T tol_p, const SolveParams &prm, int *enter)
 {
     const int lane = threadIdx.x;
     const int m = P.m, N = P.N, ldm = P.ldm, nm = P.n + P.m;
     const T tol_piv = T(prm.tol_piv);
-    if (__ballot(lane < N && P.d > tol_dual && P.nonb < nm)) return -1;
+    if (__ballot(lane < N && P.d > tol_dual && P.nonb < nm)) {
+        bool infeas = false;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            infeas |= lane + 64 * r < m && !(P.rowf[r] & (kRowDead | kRowPad)) && P.rhs[r] < -tol_p;
+        if (__ballot(infeas)) return -1;
+        return simplex<T, RB>(P, eps_opt, prm, enter);
+    }
     for (;;) {
         if (P.iters >= P.cap) return kIterLimit;
         T vl = t_inf<T>();
@@ -818,6 +832,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
         }
         if (WARM && warm_defer) {
             if (lane == 0) {
+                // Not optimal any more: the workgroup kernel that drains the
+                // deferred list then solves it from the slack basis.
+                a.status[k] = kNumerical;
                 const int slot = a.defer_base + atomicAdd(a.defer_count, 1);
                 a.defer_ids[slot] = int32_t(k);
             }
@@ -942,7 +959,7 @@ int simplex_wave_blocks_per_cu(bool fp32, int rb, bool pf, int lds)
 
 hipError_t launch_simplex_wave_warm(int rb, const SolveArgs &a, int grid, hipStream_t s)
 {
-    if (!a.warm_basis || !a.warm_rows || a.warm_m < 1) return hipErrorInvalidValue;
+    if (!a.warm_basis || (a.warm_rows && a.warm_m < 1)) return hipErrorInvalidValue;
     if (rb == 1) return launch_t<double, 1, 0, true>(a, grid, s);
     if (rb == 2) return launch_t<double, 2, 0, true>(a, grid, s);
     return hipErrorInvalidValue;

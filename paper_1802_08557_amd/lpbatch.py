@@ -30,7 +30,8 @@ EXPORTS = ("lp_batch_solve", "lp_ctx_create", "lp_ctx_destroy", "lp_options_init
            "lp_batch_solve_ex", "lp_ctx_kernel_times", "lp_last_error",
            "lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
            "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
-           "lp_hyperbox_support", "lp_ctx_tuning", "lp_batch_solve_host", "lp_batch_scale")
+           "lp_hyperbox_support", "lp_ctx_tuning", "lp_batch_solve_host", "lp_batch_scale",
+           "lp_measure_peaks")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NUM_PARAMS = 20, 256, 120, 102008
 
 
@@ -43,6 +44,13 @@ class LPOptions(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("shared", ctypes.c_int32),
                 ("row_subset", ctypes.c_void_p), ("subset_m", ctypes.c_int32),
                 ("scaling", ctypes.c_int32), ("pricing", ctypes.c_int32)]
+
+
+class LPPeaks(ctypes.Structure):
+    _fields_ = [("lds_read", ctypes.c_double), ("lds_write", ctypes.c_double),
+                ("lds_read_write", ctypes.c_double), ("lds_broadcast", ctypes.c_double),
+                ("hbm_copy", ctypes.c_double), ("clock_hz", ctypes.c_double),
+                ("num_cu", ctypes.c_int32)]
 
 
 class LPBatchError(RuntimeError):
@@ -95,6 +103,8 @@ def load():
     lib.lp_batch_solve_host.restype = i32
     lib.lp_batch_scale.argtypes = [vp, i64] + [vp] * 5 + [ctypes.c_int32, ctypes.c_int32] + [vp] * 6
     lib.lp_batch_scale.restype = i32
+    lib.lp_measure_peaks.argtypes = [vp, ctypes.POINTER(LPPeaks)]
+    lib.lp_measure_peaks.restype = i32
     for nm in ("lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
                "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
            "lp_hyperbox_support", "lp_ctx_tuning"):
@@ -380,6 +390,13 @@ class Context:
                                             self._stream(stream)))
         return value, x
 
+    def measure_peaks(self):
+        """lp_measure_peaks: measured LDS and HBM bandwidths (bytes/s), the
+        shader clock (Hz) during the LDS runs and the CU count, as a dict."""
+        p = LPPeaks()
+        _check(self.lib.lp_measure_peaks(self.handle, ctypes.byref(p)))
+        return {name: getattr(p, name) for name, _ in LPPeaks._fields_}
+
     def tuning(self):
         """[(bin, fp32, workgroup size, hbm)] of the context's autotuned launches."""
         cnt = self.lib.lp_ctx_tuning(self.handle, None, 0)
@@ -416,3 +433,4 @@ def batch_solve(batch: DeviceBatch):
                               m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
                               _ptr(status), _ptr(x), _ptr(obj)))
     return Solution(status, x, obj, None)
+

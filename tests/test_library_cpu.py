@@ -48,21 +48,28 @@ def test_options_defaults(lib):
     assert o.stats is None and o.stream is None and o.scaling == 0 and o.pricing == 0
 
 
-def test_options_layout_matches_the_header(tmp_path):
-    # The ctypes mirror of lp_options has the C struct's size and offsets.
-    from paper_1802_08557_amd.lpbatch import LPOptions
-    fields = [f[0] for f in LPOptions._fields_]
-    src = tmp_path / "layout.c"
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and field offsets of a struct of lpbatch.h, from the C compiler."""
+    src = tmp_path / f"layout_{struct}.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lpbatch.h"\nint main(void){'
-                   'printf("%zu", sizeof(lp_options));'
-                   + "".join(f'printf(" %zu", offsetof(lp_options, {f}));' for f in fields)
+                   f'printf("%zu", sizeof({struct}));'
+                   + "".join(f'printf(" %zu", offsetof({struct}, {f}));' for f in fields)
                    + "return 0;}\n")
-    exe = tmp_path / "layout"
+    exe = tmp_path / f"layout_{struct}"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
                    check=True)
-    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    assert got[0] == ctypes.sizeof(LPOptions)
-    assert got[1:] == [getattr(LPOptions, f).offset for f in fields]
+    return [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+
+
+@pytest.mark.parametrize("struct,cls", [("lp_options", "LPOptions"), ("lp_peaks", "LPPeaks")])
+def test_struct_layouts_match_the_header(tmp_path, struct, cls):
+    # The ctypes mirrors of lp_options and lp_peaks have the C structs' sizes and offsets.
+    from paper_1802_08557_amd import lpbatch
+    C = getattr(lpbatch, cls)
+    fields = [f[0] for f in C._fields_]
+    got = _c_layout(tmp_path, struct, fields)
+    assert got[0] == ctypes.sizeof(C)
+    assert got[1:] == [getattr(C, f).offset for f in fields]
 
 
 def test_null_context_and_bad_arguments_are_errors(lib):
@@ -72,6 +79,7 @@ def test_null_context_and_bad_arguments_are_errors(lib):
     assert lib.lp_ctx_create(None, 0) == lpbatch.LP_ERR_ARG
     assert lib.lp_ctx_kernel_times(None, None, None, 0) == lpbatch.LP_ERR_ARG
     assert lib.lp_batch_scale(None, 1, *([None] * 5), 4, 0, *([None] * 6)) == lpbatch.LP_ERR_ARG
+    assert lib.lp_measure_peaks(None, None) == lpbatch.LP_ERR_ARG
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd") and os.access("/dev/kfd", os.R_OK),
