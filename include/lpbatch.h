@@ -178,14 +178,23 @@ typedef enum { LP_PRICE_DANTZIG = 0, LP_PRICE_STEEPEST_EDGE = 1 } lp_pricing;
 
 #define LP_FLAG_SYNC 1u        /* wait for the stream before returning            */
 #define LP_FLAG_TIME_KERNELS 2u /* record HIP events around each kernel launched  */
-/* Uneven batches: LPs the one-wavefront kernel cannot take are grouped in
- * size bins by tableau cells ((m+1)(n+1) <= 64^2, 128^2, 256^2, larger), each
- * bin one persistent launch of the workgroup kernel whose queue hands out the
- * most expensive LPs first.  With LP_FLAG_AUTOTUNE, every bin not yet in the
- * context's table is first timed on a sample of up to 256 of its LPs for each
- * workgroup size (64, 128, 256, 512) and placement (LDS when it fits, or
- * device memory), and the fastest is kept in the context for later calls.
- * The call is then synchronous; results are as without the flag. */
+/* Workgroup-kernel launches (paper Sec. 5.1, load balancing): in a batch of
+ * mixed LP sizes every LP the one-wavefront kernel cannot take goes to ONE
+ * persistent launch of the workgroup kernel whose queue hands out the most
+ * expensive LPs first (m n (m + n)), each LP's tableau in LDS when it fits the
+ * launch's budget and in the workgroup's device-memory slot otherwise.  The
+ * planned shapes stay on the device: a later call on the same context with
+ * the same m[] and n[] uploads nothing and does not wait on the host, so it
+ * can be captured in a HIP graph (capturing the first solve of a new set of
+ * shapes fails with LP_ERR_ARG).  A batch of one size that the workgroup
+ * kernel takes is one launch as well.  With LP_FLAG_AUTOTUNE, a launch whose
+ * bin is not yet in the context's table -- size bins 0..3 by tableau cells
+ * ((m+1)(n+1) <= 64^2, 128^2, 256^2, larger) for batches of one size, bin 4
+ * for the launch of a mixed batch -- is first timed on a sample of up to 512
+ * of its LPs for each workgroup size (64, 128, 256, 512) and placement (LDS
+ * when it fits, or device memory), and the fastest is kept in the context for
+ * later calls.  The call is then synchronous; results are as without the
+ * flag. */
 #define LP_FLAG_AUTOTUNE 4u
 
 void lp_options_init(lp_options *opts);
@@ -246,8 +255,9 @@ int lp_ctx_kernel_times(lp_ctx *ctx, const char **names, float *ms, int cap);
 
 /*
  * lp_ctx_tuning -- the context's autotuned launches, up to `cap` entries of
- * 4 int32 each (HOST memory): size bin (0..3), 1 for FP32 tableaux, workgroup
- * size, 1 when tableaux go to device memory.  Returns the number of entries
+ * 4 int32 each (HOST memory): bin (0..3: size bin of a batch of one size; 4:
+ * the launch of a mixed batch), 1 for FP32 tableaux, workgroup size, 1 when
+ * tableaux go to device memory.  Returns the number of entries
  * the table holds (entries may be NULL to count), or a negative LP_ERR_* code.
  */
 int lp_ctx_tuning(lp_ctx *ctx, int32_t *entries, int cap);

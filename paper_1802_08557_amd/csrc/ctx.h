@@ -135,6 +135,21 @@ struct TuneEntry {
 
 inline int tune_key(int bin, bool fp32) { return bin * 2 + (fp32 ? 1 : 0); }
 
+// The device metadata of the last batch of mixed LP sizes that was planned
+// (shapes, offsets, id lists, in the context's `meta` buffer): a solve of the
+// same shapes reuses it without an upload, so repeat solves queue their kernels
+// without waiting on the host and can be captured in a HIP graph.  Uploads go
+// through a pinned staging buffer; the event lets the next upload wait until
+// the previous one has read it.
+struct PlanCache {
+    bool valid = false;
+    uint64_t hash = 0;          // of num, m[], n[] and the planning flags
+    const void *meta_p = nullptr;
+    size_t meta_bytes = 0;
+    PinnedBuf staging;
+    hipEvent_t uploaded = nullptr;
+};
+
 }  // namespace lpb
 
 struct lp_ctx {
@@ -150,6 +165,7 @@ struct lp_ctx {
     lpb::MlpState mlp;
     std::map<int, lpb::TuneEntry> tune;  // size bin x precision -> launch (autotuner)
     lpb::HostPipe pipe;                  // lp_batch_solve_host streams and buffers
+    lpb::PlanCache plan;                 // uploaded metadata of the last mixed-size batch
 };
 
 namespace lpb {

@@ -91,9 +91,10 @@ struct CertArgs {
     int32_t *queue, *done;
     int32_t lds_bytes;
     double tol_feas, tol_opt; // certificate tolerances (relative, as in SolveParams)
-    // Wavefront kernel only: LDS bytes per wavefront, LU blocks up to kl x kl
-    // kept in LDS (larger ones, up to 64 x 64, in the wavefront's scratch
-    // slot), and whether the shared constraint matrix is copied into LDS.
+    // Wavefront kernels only: LDS bytes per wavefront (the dense kernel: the
+    // bytes of its staged A), LU blocks up to kl x kl kept in LDS (a larger
+    // basis goes to the FP64 re-solve), and whether the shared constraint
+    // matrix is copied into LDS.
     int32_t wave_bytes, kl, stage_a;
 };
 
@@ -122,6 +123,16 @@ __host__ __device__ inline WaveCertLayout wave_cert_layout(int m, int n, int kl)
 
 hipError_t launch_certify_wave(int waves, const CertArgs &a, int grid, hipStream_t s);
 int certify_wave_blocks_per_cu(int waves, int lds_bytes);
+
+// Dense certificate (certify_dense.hip): one wavefront per LP of at most 64 x
+// 64 and certify_dense_prefetch_elems() entries, own A (not shared, not
+// screened); wave_bytes = certify_dense_a_bytes(m_max, n_max), kl <= 64.
+hipError_t launch_certify_dense(const CertArgs &a, int grid, hipStream_t s);
+int certify_dense_blocks_per_cu(int lds_bytes);
+int64_t certify_dense_a_bytes(int m_max, int n_max);
+int64_t certify_dense_lds_bytes(int m_max, int n_max, int kl);
+int certify_dense_prefetch_elems();
+hipError_t certify_dense_configure(int max_lds);
 
 hipError_t launch_certify(int nt, const CertArgs &a, int grid, hipStream_t s);
 int certify_blocks_per_cu(int nt, int lds_bytes);

@@ -49,6 +49,7 @@ struct Plan {
     int64_t num;
     bool uniform;
     int32_t m0, n0, m_max, n_max;
+    int64_t mn_max;
     bool fp32;
     int64_t ts;
 };
@@ -187,13 +188,18 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
 }
 
 
-// ---- Size bins for uneven batches ------------------------------------------
-// LPs the wavefront kernel cannot take are grouped by the cell count of their
-// tableau; each bin gets its own persistent launch of the workgroup kernel
-// with its own workgroup size and placement, from the context's tuning table
-// (filled by the autotuner) or a size heuristic.  Inside a bin the work queue
-// hands out the most expensive LPs first, so the launch ends on small ones.
+// ---- Workgroup-kernel launches and their tuning ------------------------------
+// A batch of one LP size that the wavefront kernel cannot take is one launch,
+// tuned per size bin (the cell count of its tableau).  In a batch of mixed
+// sizes every LP the wavefront kernel cannot take goes to ONE persistent
+// launch of the workgroup kernel whose queue hands out the most expensive LPs
+// first (each LP's tableau in LDS when it fits the launch's budget, else in
+// the workgroup's device-memory slot), so the launch ends on small LPs instead
+// of idling between per-size launches.  Workgroup size and placement come from
+// the context's tuning table (filled by the autotuner) or a heuristic.
 constexpr int kBins = 4;
+// Tuning-table bin of the single workgroup-kernel launch of a batch of mixed sizes.
+constexpr int kMixedBin = 4;
 
 int bin_of(int64_t m, int64_t n)
 {
@@ -204,6 +210,22 @@ int bin_of(int64_t m, int64_t n)
 // Untuned workgroup size: 512 threads for every bin (the autotuner picked 512 in
 // every bin of the 10..300 uneven batch on MI355X).
 int default_threads(int) { return 512; }
+
+// FNV-1a over the batch's shapes and the planning flags (the plan cache key).
+uint64_t shape_hash(int64_t num, const int32_t *m, const int32_t *n, uint32_t flags)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(uint64_t(num));
+    mix(flags);
+    for (int64_t k = 0; k < num; ++k) mix((uint64_t(uint32_t(m[k])) << 32) | uint32_t(n[k]));
+    return h;
+}
 
 // Estimated work of one LP: pivots grow with m + n, each pivot touches m x n cells.
 double lp_cost(int64_t m, int64_t n) { return double(m) * double(n) * double(m + n); }
@@ -485,7 +507,8 @@ int lp_ctx_create(lp_ctx **out, int device)
     }
     if (lpb::simplex_configure(ctx->max_lds) != hipSuccess ||
         lpb::simplex_wave_configure(ctx->max_lds) != hipSuccess ||
-        lpb::certify_configure(ctx->max_lds) != hipSuccess || lpb::mlp_configure() != hipSuccess) {
+        lpb::certify_configure(ctx->max_lds) != hipSuccess || lpb::certify_dense_configure(ctx->max_lds) != hipSuccess ||
+        lpb::mlp_configure() != hipSuccess) {
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: could not configure kernel LDS limits");
     }
@@ -525,6 +548,8 @@ void lp_ctx_destroy(lp_ctx *ctx)
     }
     for (hipStream_t st : {H.h2d, H.comp, H.d2h})
         if (st) (void)hipStreamDestroy(st);
+    ctx->plan.staging.release();
+    if (ctx->plan.uploaded) (void)hipEventDestroy(ctx->plan.uploaded);
     delete ctx;
 }
 
@@ -559,7 +584,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     // Shapes (host arrays) and the uniform-shape shortcut.
     Plan P;
     P.num = num_lps;
-    P.m0 = m[0]; P.n0 = n[0]; P.m_max = 0; P.n_max = 0;
+    P.m0 = m[0]; P.n0 = n[0]; P.m_max = 0; P.n_max = 0; P.mn_max = 0;
     P.uniform = true;
     int64_t sa = 0;
     for (int64_t k = 0; k < num_lps; ++k) {
@@ -571,6 +596,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         P.uniform = P.uniform && mk == P.m0 && nk == P.n0;
         P.m_max = std::max(P.m_max, mk);
         P.n_max = std::max(P.n_max, nk);
+        P.mn_max = std::max<int64_t>(P.mn_max, int64_t(mk) * nk);
         sa += int64_t(mk) * nk;
         if (sa > (int64_t(1) << 60)) return fail(LP_ERR_ARG, "batch size overflows");
     }
@@ -637,6 +663,8 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     {
         int rc = ctx->meta.ensure(sz_shape + 4 * lpb::align16(sz_ids) + sz_fp32);
         if (rc != LP_OK) return rc;
+        // A batch of one size writes id lists where a mixed batch's plan lives.
+        if (P.uniform) ctx->plan.valid = false;
     }
     char *meta = static_cast<char *>(ctx->meta.p);
     int32_t *d_wave_ids = reinterpret_cast<int32_t *>(meta + sz_shape);
@@ -665,33 +693,27 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         sp.m_max = P.m0;
         sp.n_max = P.n0;
         sp.sample_offset = 0;
-        sp.sample_count = std::min<int64_t>(num_lps, 256);
+        sp.sample_count = std::min<int64_t>(num_lps, 512);
         for (int64_t t = 0; t < sp.sample_count; ++t) samples.push_back(int32_t(t * num_lps / sp.sample_count));
         bins.push_back(sp);
     } else if (binned) {
-        std::vector<int32_t> by_bin[kBins];
-        for (int32_t k : block_ids) by_bin[bin_of(m[k], n[k])].push_back(k);
-        block_ids.clear();
-        for (int bi = kBins - 1; bi >= 0; --bi) {
-            std::vector<int32_t> &v = by_bin[bi];
-            if (v.empty()) continue;
-            std::stable_sort(v.begin(), v.end(),
-                             [&](int32_t x, int32_t y) { return lp_cost(m[x], n[x]) > lp_cost(m[y], n[y]); });
-            BinSpan sp;
-            sp.bin = bi;
-            sp.offset = int64_t(block_ids.size());
-            sp.count = int64_t(v.size());
-            sp.m_max = 0;
-            sp.n_max = 0;
-            for (int32_t k : v) { sp.m_max = std::max(sp.m_max, m[k]); sp.n_max = std::max(sp.n_max, n[k]); }
-            // Every stride-th LP of the cost-ordered bin, at most 256.
-            sp.sample_offset = int64_t(samples.size());
-            const int64_t want = std::min<int64_t>(sp.count, 256);
-            for (int64_t t = 0; t < want; ++t) samples.push_back(v[size_t(t * sp.count / want)]);
-            sp.sample_count = want;
-            block_ids.insert(block_ids.end(), v.begin(), v.end());
-            bins.push_back(sp);
-        }
+        // Every LP the wavefront kernel cannot take, in one launch, ordered by
+        // estimated work (largest first); the autotuner's sample is every
+        // stride-th LP of that order, at most 512.
+        std::stable_sort(block_ids.begin(), block_ids.end(),
+                         [&](int32_t x, int32_t y) { return lp_cost(m[x], n[x]) > lp_cost(m[y], n[y]); });
+        BinSpan sp;
+        sp.bin = kMixedBin;
+        sp.offset = 0;
+        sp.count = int64_t(block_ids.size());
+        sp.m_max = 0;
+        sp.n_max = 0;
+        for (int32_t k : block_ids) { sp.m_max = std::max(sp.m_max, m[k]); sp.n_max = std::max(sp.n_max, n[k]); }
+        sp.sample_offset = 0;
+        const int64_t want = std::min<int64_t>(sp.count, 512);
+        for (int64_t t = 0; t < want; ++t) samples.push_back(block_ids[size_t(t * sp.count / want)]);
+        sp.sample_count = want;
+        bins.push_back(sp);
     }
     if (P.uniform) {
         a.um = P.m0;
@@ -702,27 +724,53 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             HIP_TRY(hipStreamSynchronize(stream));
         }
     } else {
-        const size_t sample_at = sz_shape + 3 * lpb::align16(sz_ids);
-        std::vector<char> host(samples.empty() ? sz_shape + lpb::align16(sz_ids) + size_t(n_block) * sizeof(int32_t)
-                                                : sample_at + samples.size() * sizeof(int32_t));
-        if (!samples.empty())
-            std::copy(samples.begin(), samples.end(), reinterpret_cast<int32_t *>(host.data() + sample_at));
-        int32_t *hm = reinterpret_cast<int32_t *>(host.data());
-        int32_t *hn = hm + num_lps;
-        int64_t *ha = reinterpret_cast<int64_t *>(hn + num_lps);
-        int64_t *hr = ha + num_lps, *hc = hr + num_lps;
-        int64_t oa = 0, orr = 0, oc = 0;
-        for (int64_t k = 0; k < num_lps; ++k) {
-            hm[k] = m[k]; hn[k] = n[k];
-            ha[k] = oa; hr[k] = orr; hc[k] = oc;
-            oa += int64_t(m[k]) * n[k]; orr += m[k]; oc += n[k];
+        // Shapes, offsets and id lists of a batch of mixed sizes: reused from
+        // the previous call when it planned the same shapes (nothing to upload,
+        // so repeat solves can be captured in a HIP graph); otherwise uploaded
+        // from the context's pinned staging buffer without waiting for the copy.
+        const bool need_samples = autotune && !bins.empty() && !ctx->tune.count(lpb::tune_key(kMixedBin, P.fp32));
+        const uint32_t plan_flags = (P.fp32 ? 1u : 0u) | (auto_kernel ? 2u : 0u) | (binned ? 4u : 0u);
+        const uint64_t h = shape_hash(num_lps, m, n, plan_flags);
+        const bool hit = ctx->plan.valid && ctx->plan.hash == h && ctx->plan.meta_p == ctx->meta.p &&
+                         ctx->plan.meta_bytes == ctx->meta.bytes && !need_samples;
+        if (!hit) {
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            HIP_TRY(hipStreamIsCapturing(stream, &cap));
+            if (cap != hipStreamCaptureStatusNone)
+                return fail(LP_ERR_ARG, "a batch of mixed LP sizes can be captured in a graph only after an "
+                            "uncaptured solve of the same shapes on this context (its plan is then reused)");
+            const size_t sample_at = sz_shape + 3 * lpb::align16(sz_ids);
+            const size_t bytes = samples.empty() ? sz_shape + lpb::align16(sz_ids) + size_t(n_block) * sizeof(int32_t)
+                                                 : sample_at + samples.size() * sizeof(int32_t);
+            // The previous upload must have read the staging buffer before it is rewritten.
+            if (ctx->plan.uploaded) HIP_TRY(hipEventSynchronize(ctx->plan.uploaded));
+            else HIP_TRY(hipEventCreateWithFlags(&ctx->plan.uploaded, hipEventDisableTiming));
+            ctx->plan.valid = false;
+            int rc = ctx->plan.staging.ensure(bytes);
+            if (rc != LP_OK) return rc;
+            char *host = static_cast<char *>(ctx->plan.staging.p);
+            if (!samples.empty()) std::copy(samples.begin(), samples.end(), reinterpret_cast<int32_t *>(host + sample_at));
+            int32_t *hm = reinterpret_cast<int32_t *>(host);
+            int32_t *hn = hm + num_lps;
+            int64_t *ha = reinterpret_cast<int64_t *>(hn + num_lps);
+            int64_t *hr = ha + num_lps, *hc = hr + num_lps;
+            int64_t oa = 0, orr = 0, oc = 0;
+            for (int64_t k = 0; k < num_lps; ++k) {
+                hm[k] = m[k]; hn[k] = n[k];
+                ha[k] = oa; hr[k] = orr; hc[k] = oc;
+                oa += int64_t(m[k]) * n[k]; orr += m[k]; oc += n[k];
+            }
+            int32_t *hw = reinterpret_cast<int32_t *>(host + sz_shape);
+            std::copy(wave_ids.begin(), wave_ids.end(), hw);
+            int32_t *hb = reinterpret_cast<int32_t *>(host + sz_shape + lpb::align16(sz_ids));
+            std::copy(block_ids.begin(), block_ids.end(), hb);
+            HIP_TRY(hipMemcpyAsync(meta, host, bytes, hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipEventRecord(ctx->plan.uploaded, stream));
+            ctx->plan.valid = true;
+            ctx->plan.hash = h;
+            ctx->plan.meta_p = ctx->meta.p;
+            ctx->plan.meta_bytes = ctx->meta.bytes;
         }
-        int32_t *hw = reinterpret_cast<int32_t *>(host.data() + sz_shape);
-        std::copy(wave_ids.begin(), wave_ids.end(), hw);
-        int32_t *hb = reinterpret_cast<int32_t *>(host.data() + sz_shape + lpb::align16(sz_ids));
-        std::copy(block_ids.begin(), block_ids.end(), hb);
-        HIP_TRY(hipMemcpyAsync(meta, host.data(), host.size(), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipStreamSynchronize(stream));  // the host staging buffer goes away
         a.m = reinterpret_cast<int32_t *>(meta);
         a.n = a.m + num_lps;
         a.aoff = reinterpret_cast<int64_t *>(const_cast<int32_t *>(a.n + num_lps));
@@ -777,7 +825,26 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
         ca.tol_feas = p64.tol_feas;
         ca.tol_opt = p64.tol_opt;
         const int kmax = std::min(P_full.m_max, P_full.n_max);
-        if (kmax <= 64) {
+        const bool dense = !shared && P_full.m_max <= 64 && P_full.n_max <= 64 &&
+                           P_full.mn_max <= lpb::certify_dense_prefetch_elems();
+        if (dense) {
+            // One wavefront per LP with the next LP's input in flight; LU blocks
+            // up to 20 x 20 (a larger basis goes to the FP64 re-solve).
+            const int kl = std::min(kmax, 20);
+            const int64_t lds = lpb::certify_dense_lds_bytes(P_full.m_max, P_full.n_max, kl);
+            if (lds > ctx->max_lds) return fail(LP_ERR_ARG, "LP too large for the certificate kernel");
+            ca.wave_bytes = int32_t(lpb::certify_dense_a_bytes(P_full.m_max, P_full.n_max));
+            ca.kl = kl;
+            ca.lds_bytes = int32_t(lds);
+            ca.viol = d_viol;
+            viol_counted = true;
+            const int per_cu = lpb::certify_dense_blocks_per_cu(int(lds));
+            if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
+            const int64_t cgrid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
+            Timer t(ctx, timing, stream, "certify_fp64");
+            HIP_TRY(lpb::launch_certify_dense(ca, int(cgrid), stream));
+            t.done();
+        } else if (kmax <= 64) {
             // One wavefront per LP; LU blocks up to kl x kl in LDS (a basis with
             // more basic structurals, rare at these sizes, goes to the FP64
             // re-solve).  Shared constraints are copied into LDS once per

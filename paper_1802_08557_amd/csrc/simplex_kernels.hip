@@ -213,12 +213,27 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
                 T key = bland ? T(0) : -d;
                 if (steep) {
                     // Steepest edge: d_j^2 / (1 + sum of column j's squares
-                    // over the live rows); threads walk down their columns.
-                    T w = T(1);
-                    for (int i = 0; i < m; ++i) {
-                        const T t = tab[(int64_t)i * ld + j];
-                        w = (P.rowf[i] & ROW_DEAD) ? w : fma(t, t, w);
+                    // over the live rows); threads walk down their columns,
+                    // rows i summed into partial sum i mod R, the partial sums
+                    // then added in order -- the wavefront kernel's order, so
+                    // both kernels choose the same column.
+                    constexpr int R = 16 / int(sizeof(T));
+                    T acc[R];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) acc[q] = T(0);
+                    for (int i0 = 0; i0 < m; i0 += R) {
+#pragma unroll
+                        for (int q = 0; q < R; ++q) {
+                            const int i = i0 + q;
+                            if (i < m && !(P.rowf[i] & ROW_DEAD)) {
+                                const T t = tab[(int64_t)i * ld + j];
+                                acc[q] = fma(t, t, acc[q]);
+                            }
+                        }
                     }
+                    T w = T(1);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) w += acc[q];
                     key = -(d * d / w);
                 }
                 if (key < k1 || (key == k1 && bj < k2)) { k1 = key; k2 = bj; p = j; }

@@ -1,7 +1,9 @@
 """Repeat solves captured in a HIP graph (through torch.cuda.CUDAGraph) give
 the eager results on every replay.  Uniform and shared batches plan without
-any host synchronisation, so one solve call (several kernels, counters that
-reset themselves) is capturable once its buffers exist."""
+any host synchronisation, and a batch of mixed sizes reuses the plan an
+uncaptured solve of the same shapes left on the device, so one solve call
+(several kernels, counters that reset themselves) is capturable once its
+buffers exist."""
 import numpy as np
 import pytest
 
@@ -50,6 +52,25 @@ def test_graph_replay_uniform(env, precision):
     ref = ctx.solve(db, stats=True, precision=precision)
     torch.cuda.synchronize()
     want = (ref.status.cpu().numpy(), ref.obj.cpu().numpy(), ref.x.cpu().numpy())
+    out = ctx.solve(db, stats=True, precision=precision)
+    torch.cuda.synchronize()
+    fn = lambda o: ctx.solve(db, stats=True, precision=precision, out=o)
+    for st, obj, x in _graph_replays(torch, fn, out):
+        np.testing.assert_array_equal(st, want[0])
+        np.testing.assert_array_equal(obj, want[1])
+        np.testing.assert_array_equal(x, want[2])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_mixed_sizes(env, precision):
+    torch, lpbatch, ctx = env
+    bt = W.uneven_batch(600, seed=88, lo=10, hi=160)
+    db = lpbatch.DeviceBatch.from_host(bt)
+    ref = ctx.solve(db, stats=True, precision=precision)
+    torch.cuda.synchronize()
+    want = (ref.status.cpu().numpy(), ref.obj.cpu().numpy(), ref.x.cpu().numpy())
+    st = ref.stats.cpu().numpy()
+    assert np.any(st[:, 6] == 1) and np.any(st[:, 6] >= 2)  # both kernels in the graph
     out = ctx.solve(db, stats=True, precision=precision)
     torch.cuda.synchronize()
     fn = lambda o: ctx.solve(db, stats=True, precision=precision, out=o)

@@ -158,18 +158,20 @@ def test_edge_cases(ctx):
     assert st3[0] == oracle.ITERATION_LIMIT
 
 
-def test_placement_and_block_size_are_bitwise_identical(ctx):
+@pytest.mark.parametrize("pricing", [0, 1])
+def test_placement_and_block_size_are_bitwise_identical(ctx, pricing):
     """Every kernel variant (one wavefront per LP, workgroups of 64..512
     threads, tableau in LDS or HBM) computes the same element updates in the
-    same order: bitwise-identical results expose races and missing barriers."""
+    same order, and under steepest-edge pricing the same column weights:
+    bitwise-identical results expose races and missing barriers."""
     bt = W.Batch(*[np.concatenate(v) for v in zip(
         *[(p.A, p.b, p.c, p.sense, p.m, p.n) for p in
           (W.config1(300), W.phase1_batch(200, 30, 40, seed=5), W.uneven_batch(60, seed=9, lo=10, hi=120))])],
         name="mixed")
-    runs = [((0, 0), run(ctx, bt))]  # automatic: one wavefront per small LP
+    runs = [((0, 0), run(ctx, bt, pricing=pricing))]  # automatic: one wavefront per small LP
     for placement in (1, 2):
         for nt in (64, 128, 256, 512):
-            runs.append(((placement, nt), run(ctx, bt, placement=placement, block_threads=nt)))
+            runs.append(((placement, nt), run(ctx, bt, placement=placement, block_threads=nt, pricing=pricing)))
     assert np.any(runs[0][1][3][:, 6] == 1)
     (k0, (st0, obj0, x0, s0)) = runs[0]
     for k, (st, obj, x, s) in runs[1:]:
