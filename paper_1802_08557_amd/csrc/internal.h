@@ -222,7 +222,7 @@ hipError_t simplex_wave_configure(int max_lds);
 // an LDS-resident tableau would start.  Host and device compute the same layout.
 
 struct LdsLayout {
-    int64_t ctrl, basis, nonb, rowf, colrow, pcol, prow, tab, end_aux;
+    int64_t ctrl, basis, nonb, rowf, colrow, pcol, prow, pcol2, prow2, tab, end_aux;
 };
 
 // ctrl_bytes: size of the control block (type dependent, passed by the caller).
@@ -236,7 +236,9 @@ __host__ __device__ inline LdsLayout lds_layout(int m, int ncol_max, int64_t tsi
     L.colrow = align16(L.rowf + 4 * (int64_t)m);
     L.pcol = align16(L.colrow + 4 * (int64_t)m);
     L.prow = align16(L.pcol + tsize * (int64_t)(m + 1));
-    L.tab = align16(L.prow + tsize * (int64_t)(ncol_max + 1));
+    L.pcol2 = align16(L.prow + tsize * (int64_t)(ncol_max + 1));
+    L.prow2 = align16(L.pcol2 + tsize * (int64_t)(m + 1));
+    L.tab = align16(L.prow2 + tsize * (int64_t)(ncol_max + 1));
     L.end_aux = L.tab;
     return L;
 }

@@ -120,31 +120,42 @@ struct LP {
     // LDS arrays
     Ctrl<T> *sh;
     int *basis, *nonb, *rowf, *colrow;
-    T *pcol, *prow;
+    T *pcol, *prow;    // pivot column and (scaled) pivot row of a pivot
+    T *pcol2, *prow2;  // the same for the second pivot of a fused pair
     T *tab;  // LDS or HBM
     // counters (uniform across the workgroup)
     int iters, it1, degp, cap;
 };
 
-// Step 3: pivot on (l, e).  Every thread takes part; ends with a barrier.
+// Step 3's vectors for a pivot on (l, e) of the current tableau: the scaled
+// pivot row prow_j = t_lj / PE (1 / PE in column e) and the pivot column
+// pcol_i = t_ie (0 for dropped rows; row m is the objective row).  No barrier.
 template <typename T, int NT>
-__device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
+__device__ __forceinline__ void pivot_vectors(LP<T, NT> &P, int l, int e)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int W = NT / 64;
-    T *tab = P.tab;
+    const int tid = threadIdx.x;
+    const T *tab = P.tab;
     const int ld = P.ld, C = P.C, m = P.m;
     const T pe = tab[(int64_t)l * ld + e];
     for (int j = tid; j < C; j += NT)
         P.prow[j] = (j == e) ? T(1) / pe : tab[(int64_t)l * ld + j] / pe;
     for (int i = tid; i <= m; i += NT)
         P.pcol[i] = (i < m && (P.rowf[i] & ROW_DEAD)) ? T(0) : tab[(int64_t)i * ld + e];
-    __syncthreads();
-    // Sweep: each wavefront takes whole rows, every lane 16 bytes (R entries)
-    // per access and U accesses in flight -- all loads, then the fmas, then
-    // all stores.  Rows start 16-byte aligned (tableau_ld); the entries past C
-    // up to the row stride are padding, updated with whatever they hold and
-    // never read back (the pivot-row buffer is padded the same way).
+}
+
+// Step 3's sweep for the pivot whose vectors are in P.prow / P.pcol: each
+// wavefront takes whole rows, every lane 16 bytes (R entries) per access and
+// U accesses in flight -- all loads, then the fmas, then all stores.  Rows
+// start 16-byte aligned (tableau_ld); the entries past C up to the row stride
+// are padding, updated with whatever they hold and never read back (the
+// pivot-row buffers are padded the same way).  No barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void sweep1(LP<T, NT> &P, int l, int e)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int W = NT / 64;
+    T *tab = P.tab;
+    const int ld = P.ld, C = P.C, m = P.m;
     using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
     constexpr int R = 16 / int(sizeof(T));
     constexpr int U = 4;
@@ -180,12 +191,80 @@ __device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
             }
         }
     }
-    if (tid == 0) {
+}
+
+// Step 3: pivot on (l, e).  Every thread takes part; ends with a barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
+{
+    pivot_vectors<T, NT>(P, l, e);
+    __syncthreads();
+    sweep1<T, NT>(P, l, e);
+    if (threadIdx.x == 0) {
         const int t = P.basis[l];
         P.basis[l] = P.nonb[e];
         P.nonb[e] = t;
     }
     __syncthreads();
+}
+
+// Two consecutive pivots, (l1, e1) and then (l2, e2) of the tableau that the
+// first leaves, in ONE pass over the tableau: every entry is read once,
+// updated by the first pivot's rule and then by the second's -- the same
+// operations in the same order as two separate sweeps, so the result is the
+// same bit for bit -- and written once, which halves the tableau traffic of
+// the pair.  P.prow / P.pcol hold the first pivot's vectors, P.prow2 / P.pcol2
+// the second's (computed from the first's without the tableau being swept).
+// No barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void sweep2(LP<T, NT> &P, int l1, int e1, int l2, int e2)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int W = NT / 64;
+    T *tab = P.tab;
+    const int ld = P.ld, C = P.C, m = P.m;
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int R = 16 / int(sizeof(T));
+    constexpr int U = 4;
+    const int nv = (C + R - 1) / R;
+    const V *pr1 = reinterpret_cast<const V *>(P.prow);
+    const V *pr2 = reinterpret_cast<const V *>(P.prow2);
+    for (int i = wave; i <= m; i += W) {
+        V *row = reinterpret_cast<V *>(tab + (int64_t)i * ld);
+        if (i == l2) {
+            for (int k = lane; k < nv; k += 64) row[k] = pr2[k];
+            continue;
+        }
+        const bool first = i == l1;
+        const T f1 = P.pcol[i], f2 = P.pcol2[i];
+        for (int k0 = lane; k0 < nv; k0 += 64 * U) {
+            V v[U], w1[U], w2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 64 * u;
+                if (k < nv) {
+                    if (!first) v[u] = row[k];
+                    w1[u] = pr1[k];
+                    w2[u] = pr2[k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 64 * u;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int j = k * R + r;
+                    T t = first ? w1[u][r] : fma(-f1, w1[u][r], (j == e1) ? T(0) : v[u][r]);
+                    v[u][r] = fma(-f2, w2[u][r], (j == e2) ? T(0) : t);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 64 * u;
+                if (k < nv) row[k] = v[u];
+            }
+        }
+    }
 }
 
 // Steps 1-3 until a halt condition.  Returns ST_OPTIMAL, ST_UNBOUNDED or ST_ITER;
@@ -194,7 +273,7 @@ template <typename T, int NT>
 __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParams &prm, int *enter)
 {
     const int tid = threadIdx.x;
-    const int m = P.m, N = P.N, ld = P.ld, nm = P.n + P.m;
+    const int m = P.m, N = P.N, C = P.C, ld = P.ld, nm = P.n + P.m;
     const T tol_piv = T(prm.tol_piv);
     T *tab = P.tab;
     int deg_run = 0;
@@ -257,8 +336,94 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
         block_argmin<T, NT>(k1, k2, p, P.sh);
         if (p < 0) { *enter = P.nonb[e]; return ST_UNBOUNDED; }
         if (k1 == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
-        pivot<T, NT>(P, p, e);
-        ++P.iters;
+        const int l = p;
+        if (prm.pricing == 1 || P.iters + 1 >= P.cap) {
+            pivot<T, NT>(P, l, e);
+            ++P.iters;
+            continue;
+        }
+        // Look one pivot ahead.  The tableau the pivot on (l, e) leaves is
+        // t'_ij = fma(-pcol_i, prow_j, t_ij) (0 for t_ij in column e; prow_j
+        // in row l), so Steps 1 and 2 of the next iteration need only the
+        // objective row, one column and the right-hand sides of it, computed
+        // here from the pivot's vectors without sweeping the tableau.  When
+        // they find a second pivot both go through one sweep (sweep2).
+        pivot_vectors<T, NT>(P, l, e);
+        if (tid == 0) {
+            const int t = P.basis[l];
+            P.basis[l] = P.nonb[e];
+            P.nonb[e] = t;
+        }
+        __syncthreads();
+        // Step 1 of the next iteration (column e now holds the variable that
+        // left; its reduced cost -d_e / PE is negative, so e2 != e).
+        const bool bland2 = prm.k_deg > 0 && deg_run >= prm.k_deg;
+        const T fm = P.pcol[m];
+        k1 = t_inf<T>(); k2 = BIG; p = -1;
+        for (int j = tid; j < N; j += NT) {
+            const T d = fma(-fm, P.prow[j], (j == e) ? T(0) : obj[j]);
+            const int bj = P.nonb[j];
+            if (d > eps_opt && bj < nm) {
+                const T key = bland2 ? T(0) : -d;
+                if (key < k1 || (key == k1 && bj < k2)) { k1 = key; k2 = bj; p = j; }
+            }
+        }
+        block_argmin<T, NT>(k1, k2, p, P.sh);
+        const int e2 = p;
+        int l2 = -1;
+        if (e2 >= 0) {
+            // Step 2 of the next iteration.
+            k1 = t_inf<T>(); k2 = BIG; p = -1;
+            const T pc2 = P.prow[e2], prhs = P.prow[N];
+            for (int i = tid; i < m; i += NT) {
+                if (P.rowf[i] & ROW_DEAD) continue;
+                const T a = (i == l) ? pc2 : fma(-P.pcol[i], pc2, tab[(int64_t)i * ld + e2]);
+                if (a > tol_piv) {
+                    const T bi = (i == l) ? prhs : fma(-P.pcol[i], prhs, tab[(int64_t)i * ld + N]);
+                    const T th = (bi > T(0) ? bi : T(0)) / a;
+                    const int bb = P.basis[i];
+                    if (th < k1 || (th == k1 && bb < k2)) { k1 = th; k2 = bb; p = i; }
+                }
+            }
+            block_argmin<T, NT>(k1, k2, p, P.sh);
+            l2 = p;
+        }
+        if (l2 < 0) {
+            // Optimal or unbounded after this pivot: it goes alone, and the
+            // next iteration reaches the same outcome.
+            sweep1<T, NT>(P, l, e);
+            __syncthreads();
+            ++P.iters;
+            continue;
+        }
+        if (k1 == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
+        // The second pivot's vectors, entry by entry as pivot_vectors would
+        // compute them from the swept tableau.
+        {
+            const T pc2 = P.prow[e2];
+            const T pe2 = (l2 == l) ? pc2 : fma(-P.pcol[l2], pc2, tab[(int64_t)l2 * ld + e2]);
+            const T f2 = P.pcol[l2];
+            for (int j = tid; j < C; j += NT) {
+                const T t = (l2 == l) ? P.prow[j]
+                                      : fma(-f2, P.prow[j], (j == e) ? T(0) : tab[(int64_t)l2 * ld + j]);
+                P.prow2[j] = (j == e2) ? T(1) / pe2 : t / pe2;
+            }
+            for (int i = tid; i <= m; i += NT) {
+                T t = T(0);
+                if (!(i < m && (P.rowf[i] & ROW_DEAD)))
+                    t = (i == l) ? pc2 : fma(-P.pcol[i], pc2, tab[(int64_t)i * ld + e2]);
+                P.pcol2[i] = t;
+            }
+        }
+        __syncthreads();
+        sweep2<T, NT>(P, l, e, l2, e2);
+        if (tid == 0) {
+            const int t = P.basis[l2];
+            P.basis[l2] = P.nonb[e2];
+            P.nonb[e2] = t;
+        }
+        __syncthreads();
+        P.iters += 2;
     }
 }
 
@@ -688,6 +853,8 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         P.colrow = reinterpret_cast<int *>(smem + L.colrow);
         P.pcol = reinterpret_cast<T *>(smem + L.pcol);
         P.prow = reinterpret_cast<T *>(smem + L.prow);
+        P.pcol2 = reinterpret_cast<T *>(smem + L.pcol2);
+        P.prow2 = reinterpret_cast<T *>(smem + L.prow2);
         if (L.tab > int64_t(a.lds_bytes)) {
             reject_lp<T, NT>(P, a);
             __syncthreads();
