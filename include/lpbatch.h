@@ -214,6 +214,38 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
                       const lp_options *opts);
 
 /*
+ * lp_batch_solve_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the solve of lp_batch_solve_ex with default options in FP64 for
+ * a batch of ONE shape (every LP m x n, so m and n are scalars here) that the
+ * one-wavefront kernel takes -- n <= 64, m <= 128, the m x n FP64 tableau in a
+ * CU's LDS -- with the same kernels and bit-for-bit the same results.
+ *
+ * A, b, c, sense, status, x, obj: DEVICE pointers, laid out as for
+ * lp_batch_solve_ex (uniform shape: LP k's A at k*m*n, b and sense at k*m, c and
+ * x at k*n); stats: optional DEVICE int32 [num_lps][LP_STATS_WIDTH] or NULL.
+ * The work is queued on `stream` (hipStream_t; NULL: null stream) and the call
+ * returns without waiting; the caller keeps the buffers alive until then.
+ *
+ * The call allocates nothing: its work counters, the list of LPs the
+ * wavefront kernel defers (rows >= after normalisation add surplus columns
+ * past 64) and the workgroup-kernel tableau slots that solve those live in a
+ * statically allocated 16 MiB device array that each device holds from the
+ * moment the library is loaded there until the process ends.  Limits:
+ * num_lps <= 2^20 (LP_ERR_ARG beyond); the shape limits above (LP_ERR_ARG).
+ * Every call on a device shares that device's array and the array keeps the
+ * last call's contents (the call clears what must start at zero): calls that
+ * overlap on one device -- on different streams or host threads, or through
+ * different contexts -- race and must not be issued.  Returns LP_OK or a
+ * negative LP_ERR_* code (LP_ERR_HIP also when the array's device address
+ * could not be looked up at lp_ctx_create).
+ */
+int lp_batch_solve_noalloc(lp_ctx *ctx, int64_t num_lps, const double *A, const double *b,
+                           const double *c, const int8_t *sense, int32_t m, int32_t n,
+                           int32_t *status, double *x, double *obj, int32_t *stats,
+                           void *stream);
+
+/*
  * lp_batch_solve_host -- a batch held in HOST memory, streamed through the
  * device in chunks (paper Sec. 5.1, Algorithm 1: the batch is cut into chunks
  * that fit the device, each copied over, solved and copied back; and the

@@ -166,6 +166,8 @@ struct lp_ctx {
     std::map<int, lpb::TuneEntry> tune;  // size bin x precision -> launch (autotuner)
     lpb::HostPipe pipe;                  // lp_batch_solve_host streams and buffers
     lpb::PlanCache plan;                 // uploaded metadata of the last mixed-size batch
+    void *noalloc = nullptr;             // this device's copy of lp_batch_solve_noalloc's scratch
+    int noalloc_err = 0;                 // hipError_t of its address lookup
 };
 
 namespace lpb {

@@ -191,6 +191,16 @@ hipError_t launch_ldexp(int64_t count, const double *in, const int32_t *e, int64
 // Bland index convention shared by every kernel: structural j -> j, the
 // slack/surplus of row i -> n + i, the artificial of row i -> n + m + i.
 
+// Statically allocated device scratch of lp_batch_solve_noalloc (noalloc.hip):
+// 256 bytes of work counters, the deferred-LP list (kNoAllocMaxLps entries),
+// then the workgroup kernel's tableau slots.
+constexpr int64_t kNoAllocBytes = int64_t(16) << 20;
+constexpr int64_t kNoAllocMaxLps = int64_t(1) << 20;
+constexpr int64_t kNoAllocIdsAt = 256;
+constexpr int64_t kNoAllocSlotsAt = kNoAllocIdsAt + 4 * kNoAllocMaxLps;
+// Device address of this device's copy (the current device's).
+hipError_t noalloc_scratch_address(void **ptr);
+
 // Launchers (simplex_kernels.hip).  Return the hipError_t of the launch.
 hipError_t launch_zero_i32(int32_t *p, int count, hipStream_t s);
 hipError_t launch_set_i32(int32_t *p, int32_t value, hipStream_t s);

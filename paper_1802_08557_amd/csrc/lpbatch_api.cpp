@@ -121,10 +121,14 @@ int launch_wave(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, PassCounters pc
     return LP_OK;
 }
 
+// slot_mem / slot_cap: device memory for the workgroup kernel's tableau slots
+// given by the caller (the grid shrinks to what fits); NULL: the context's
+// scratch, grown as needed.
 int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &opts, PassCounters pc,
                const int32_t *wave_ids, int64_t n_wave, int wm_max, int wn_max, int64_t n_block,
                int32_t *defer_ids, const int32_t *list_ids, const int32_t *list_count,
-               hipStream_t stream, bool timing, const char *wname, const char *bname)
+               hipStream_t stream, bool timing, const char *wname, const char *bname,
+               char *slot_mem = nullptr, int64_t slot_cap = 0)
 {
     const bool fp32 = P.fp32;
     const int64_t ts = P.ts;
@@ -156,13 +160,22 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
     // When the wavefront kernel was offered every LP, this launch only drains
     // the few it deferred: one workgroup per CU is plenty and keeps its end cheap.
     const int64_t slots = n_wave > 0 && n_block == 0 ? ctx->num_cu : int64_t(per_cu) * ctx->num_cu;
-    const int64_t grid = std::min<int64_t>(P.num, slots);
+    int64_t grid = std::min<int64_t>(P.num, slots);
     const bool need_hbm = !want_lds || tab_worst > tab_common;
     if (need_hbm) {
         a.slot_bytes = lpb::align16(tab_worst);
-        int rc = ctx->scratch.ensure(size_t(a.slot_bytes) * size_t(grid));
-        if (rc != LP_OK) return rc;
-        a.scratch = static_cast<char *>(ctx->scratch.p);
+        if (slot_mem) {
+            const int64_t fit = slot_cap / a.slot_bytes;
+            if (fit < 1)
+                return fail(LP_ERR_ARG, "a %lld-byte tableau slot exceeds the %lld bytes available",
+                            (long long)a.slot_bytes, (long long)slot_cap);
+            grid = std::min(grid, fit);
+            a.scratch = slot_mem;
+        } else {
+            int rc = ctx->scratch.ensure(size_t(a.slot_bytes) * size_t(grid));
+            if (rc != LP_OK) return rc;
+            a.scratch = static_cast<char *>(ctx->scratch.p);
+        }
     }
     a.queue = pc.bq;
     a.done = pc.bd;
@@ -512,6 +525,12 @@ int lp_ctx_create(lp_ctx **out, int device)
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: could not configure kernel LDS limits");
     }
+    // This device's copy of the no-allocation entry point's static scratch:
+    // its device address, looked up with the device current (the array's
+    // host-side name is not a device address).  A failure only disables
+    // lp_batch_solve_noalloc, which then reports it.
+    ctx->noalloc_err = int(lpb::noalloc_scratch_address(&ctx->noalloc));
+    if (ctx->noalloc_err != hipSuccess) ctx->noalloc = nullptr;
     int rc = ctx->counters.ensure(4096);
     if (rc == LP_OK && (lpb::launch_zero_i32(static_cast<int32_t *>(ctx->counters.p), 1024, nullptr) != hipSuccess ||
                         hipStreamSynchronize(nullptr) != hipSuccess))
@@ -941,6 +960,61 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
     ctx->counters_dirty = false;
     if (opts.flags & LP_FLAG_SYNC) HIP_TRY(hipStreamSynchronize(stream));
     return LP_OK;
+}
+
+int lp_batch_solve_noalloc(lp_ctx *ctx, int64_t num_lps, const double *A, const double *b, const double *c,
+                           const int8_t *sense, int32_t m, int32_t n, int32_t *status, double *x, double *obj,
+                           int32_t *stats, void *stream_p)
+{
+    if (!ctx) return fail(LP_ERR_ARG, "lp_batch_solve_noalloc: ctx is NULL");
+    if (num_lps < 0 || num_lps > lpb::kNoAllocMaxLps)
+        return fail(LP_ERR_ARG, "lp_batch_solve_noalloc: num_lps = %lld outside 0..%lld", (long long)num_lps,
+                    (long long)lpb::kNoAllocMaxLps);
+    if (num_lps == 0) return LP_OK;
+    if (!A || !b || !c || !sense || !status || !x || !obj)
+        return fail(LP_ERR_ARG, "lp_batch_solve_noalloc: a batch pointer is NULL");
+    if (m < 1 || n < 1) return fail(LP_ERR_ARG, "lp_batch_solve_noalloc: m = %d, n = %d (both must be >= 1)", m, n);
+    if (!wave_fit(ctx, m, n, false, false))
+        return fail(LP_ERR_ARG, "lp_batch_solve_noalloc: LPs of %d x %d exceed one wavefront's tableau "
+                    "(at most 64 columns and 128 rows, in LDS)", m, n);
+    if (!ctx->noalloc)
+        return fail(LP_ERR_HIP, "lp_batch_solve_noalloc: no device address for the static scratch (%s)",
+                    hipGetErrorString(hipError_t(ctx->noalloc_err)));
+    // A deferred LP (more columns than the wavefront holds once >= rows add
+    // their surplus columns) needs one workgroup-kernel slot at least.
+    const int64_t slot = lpb::align16(int64_t(m + 1) * lpb::tableau_ld(n + m + 1, 8) * 8);
+    if (slot > lpb::kNoAllocBytes - lpb::kNoAllocSlotsAt)
+        return fail(LP_ERR_ARG, "lp_batch_solve_noalloc: LPs of %d x %d need a larger tableau slot", m, n);
+    DeviceGuard g(ctx->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_p);
+
+    Plan P;
+    P.num = num_lps;
+    P.uniform = true;
+    P.m0 = P.m_max = m;
+    P.n0 = P.n_max = n;
+    P.mn_max = int64_t(m) * n;
+    P.fp32 = false;
+    P.ts = 8;
+    lp_options opts;
+    lp_options_init(&opts);
+    lpb::SolveArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.A = A; a.b = b; a.c = c; a.sense = sense;
+    a.status = status; a.x = x; a.obj = obj;
+    a.stats = stats;
+    a.prm = fill_params(opts, false);
+    a.um = m;
+    a.un = n;
+    // Scratch: the counters start at zero (cleared here by a kernel; every
+    // launch returns its counters to zero when it ends).
+    char *base = static_cast<char *>(ctx->noalloc);
+    int32_t *cnt = reinterpret_cast<int32_t *>(base);
+    HIP_TRY(lpb::launch_zero_i32(cnt, 64, stream));
+    PassCounters pc{cnt + 0, cnt + 1, cnt + 2, cnt + 3, cnt + 4};
+    int32_t *defer_ids = reinterpret_cast<int32_t *>(base + lpb::kNoAllocIdsAt);
+    return queue_pass(ctx, P, a, opts, pc, nullptr, num_lps, m, n, 0, defer_ids, nullptr, nullptr, stream, false,
+                      "", "", base + lpb::kNoAllocSlotsAt, lpb::kNoAllocBytes - lpb::kNoAllocSlotsAt);
 }
 
 int lp_batch_scale(lp_ctx *ctx, int64_t num_lps, const double *A, const double *b, const double *c,

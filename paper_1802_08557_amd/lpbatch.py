@@ -31,7 +31,7 @@ EXPORTS = ("lp_batch_solve", "lp_ctx_create", "lp_ctx_destroy", "lp_options_init
            "lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
            "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
            "lp_hyperbox_support", "lp_ctx_tuning", "lp_batch_solve_host", "lp_batch_scale",
-           "lp_measure_peaks")
+           "lp_measure_peaks", "lp_batch_solve_noalloc")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NUM_PARAMS = 20, 256, 120, 102008
 
 
@@ -105,6 +105,8 @@ def load():
     lib.lp_batch_scale.restype = i32
     lib.lp_measure_peaks.argtypes = [vp, ctypes.POINTER(LPPeaks)]
     lib.lp_measure_peaks.restype = i32
+    lib.lp_batch_solve_noalloc.argtypes = [vp, i64] + [vp] * 4 + [ctypes.c_int32] * 2 + [vp] * 5
+    lib.lp_batch_solve_noalloc.restype = i32
     for nm in ("lp_mlp_init", "lp_mlp_set_params", "lp_mlp_get_params", "lp_mlp_infer",
                "lp_mlp_grads", "lp_mlp_train_step", "lp_mlp_save", "lp_mlp_load",
            "lp_hyperbox_support", "lp_ctx_tuning"):
@@ -244,6 +246,32 @@ class Context:
             self.handle, N, _ptr(batch.A), _ptr(batch.b), _ptr(batch.c), _ptr(batch.sense),
             m.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
             _ptr(status), _ptr(x), _ptr(obj), ctypes.byref(o)))
+        return Solution(status, x, obj, st)
+
+    def solve_noalloc(self, batch: DeviceBatch, *, stats=False, stream=None, out=None) -> Solution:
+        """Queue lp_batch_solve_noalloc (FP64, default options, one m x n shape
+        taken by the one-wavefront kernel; nothing is allocated by the library;
+        outputs are allocated here unless `out` is given)."""
+        import torch
+        dev = batch.A.device
+        N = batch.num_lps
+        if N and not (np.all(batch.m == batch.m[0]) and np.all(batch.n == batch.n[0])):
+            raise ValueError("solve_noalloc needs every LP of one shape")
+        m0 = int(batch.m[0]) if N else 1
+        n0 = int(batch.n[0]) if N else 1
+        if out is None:
+            status = torch.empty(N, dtype=torch.int32, device=dev)
+            x = torch.empty(N * n0, dtype=torch.float64, device=dev)
+            obj = torch.empty(N, dtype=torch.float64, device=dev)
+            st = torch.empty((N, STATS_WIDTH), dtype=torch.int32, device=dev) if stats else None
+        else:
+            status, x, obj, st = out.status, out.x, out.obj, out.stats
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(self.lib.lp_batch_solve_noalloc(
+            self.handle, N, _ptr(batch.A), _ptr(batch.b), _ptr(batch.c), _ptr(batch.sense), m0, n0,
+            _ptr(status), _ptr(x), _ptr(obj), st.data_ptr() if st is not None else None,
+            ctypes.c_void_p(stream.cuda_stream)))
         return Solution(status, x, obj, st)
 
     def scale(self, batch: DeviceBatch, passes: int, stream=None):
