@@ -85,18 +85,19 @@ __device__ __forceinline__ void update_vec(V &v, const V &w, T prow)
     for (int r = 0; r < R; ++r) v[r] = fma(-w[r], prow, v[r]);
 }
 
+// Step 3, register part: the scaled pivot row (returned; lane j's entry
+// prow_j = t_lj / PE, 1 / PE in column e), the objective row and every
+// right-hand side updated in their owners' registers, and the index arrays
+// swapped.  P.pcol must hold the pivot column (0 for dead and padding rows).
+// rowv: lane j's entry t_lj of the pivot row in the current tableau.
 template <typename T, int RB>
-__device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
+__device__ __forceinline__ T pivot_head(WaveLP<T, RB> &P, int l, int e, T rowv)
 {
-    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int R = 16 / int(sizeof(T));
-    constexpr int G = 16 / R;  // vectors per group of 16 rows
     const int lane = threadIdx.x;
-    const int m = P.m, C = P.C, ldm = P.ldm;
-    T *tab = P.tab;
+    const int m = P.m, C = P.C;
     const T pe = row_get<RB>(P.pcol, l);
     T prow = T(0);
-    if (lane < C) prow = (lane == e) ? T(1) / pe : tab[lane * ldm + l] / pe;
+    if (lane < C) prow = (lane == e) ? T(1) / pe : rowv / pe;
     const T de = lane_get(P.d, e);
     if (lane < C) P.d = fma(-de, prow, (lane == e) ? T(0) : P.d);
     // Right-hand sides: the objective row's (uniform) and every row's, in the
@@ -108,13 +109,31 @@ __device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
         const int i = lane + 64 * r;
         if (i < m) P.rhs[r] = (i == l) ? prow_rhs : fma(-P.pcol[r], prow_rhs, P.rhs[r]);
     }
-    // Sweep this lane's column in 16-byte vectors, G vectors (16 rows) per
-    // group.  The same rows of the pivot column are read from column e by
-    // every lane (one broadcast address per load); lane e rewrites column e
-    // in the same sweep, but only rows whose pivot-column values every lane
-    // has already read, since a wavefront's LDS accesses complete in program
-    // order.  The pivot row and the swapped column are rewritten afterwards;
-    // padding rows past m take whatever values and are never read back.
+    const int bl = row_get<RB>(P.basis, l);
+    const int ne = lane_get(P.nonb, e);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (lane + 64 * r == l) P.basis[r] = ne;
+    if (lane == e) P.nonb = bl;
+    return prow;
+}
+
+// Step 3, LDS part: sweep this lane's column in 16-byte vectors, G vectors
+// (16 rows) per group.  The same rows of the pivot column are read from
+// column e by every lane (one broadcast address per load); lane e rewrites
+// column e in the same sweep, but only rows whose pivot-column values every
+// lane has already read, since a wavefront's LDS accesses complete in program
+// order.  The pivot row and the swapped column are rewritten afterwards;
+// padding rows past m take whatever values and are never read back.
+template <typename T, int RB>
+__device__ __forceinline__ void pivot_sweep(WaveLP<T, RB> &P, int l, int e, T prow)
+{
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int R = 16 / int(sizeof(T));
+    constexpr int G = 16 / R;  // vectors per group of 16 rows
+    const int lane = threadIdx.x;
+    const int m = P.m, C = P.C, ldm = P.ldm;
+    T *tab = P.tab;
     if (lane < C) {
         V *col = reinterpret_cast<V *>(tab + lane * ldm);
         const V *pc = reinterpret_cast<const V *>(tab + e * ldm);
@@ -146,12 +165,90 @@ __device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
         if (i < m) tab[e * ldm + i] = (i == l) ? pre : fma(-P.pcol[r], pre, T(0));
     }
     if (lane < C) tab[lane * ldm + l] = prow;
-    const int bl = row_get<RB>(P.basis, l);
-    const int ne = lane_get(P.nonb, e);
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void pivot(WaveLP<T, RB> &P, int l, int e)
+{
+    const int lane = threadIdx.x;
+    const T rowv = (lane < P.C) ? P.tab[lane * P.ldm + l] : T(0);
+    const T prow = pivot_head<T, RB>(P, l, e, rowv);
+    pivot_sweep<T, RB>(P, l, e, prow);
+}
+
+// Two consecutive pivots in one sweep of the columns: (l1, e1), whose row
+// vector is prow1 and column P.pcol1 (row owners), then (l2, e2) of the
+// tableau the first leaves, with row vector prow2 and column pcol2.  Both
+// pivots' register parts are done.  Every entry is read once, takes the
+// first pivot's update and then the second's, and is written once; the
+// second pivot column's entries t'_ie2 = fma(-t_ie1, prow1_e2, t_ie2) are
+// formed from both columns' broadcast reads exactly as the first sweep would
+// have written them.  Rows l1 and l2 and columns e1 and e2, which the two
+// pivots replace rather than update, are rewritten afterwards with the
+// values two separate pivots leave there, so the result is the same bit for
+// bit.
+template <typename T, int RB>
+__device__ __forceinline__ void pivot_sweep2(WaveLP<T, RB> &P, int l1, int e1, T prow1, const T (&pcol1)[RB],
+                                             int l2, int e2, T prow2)
+{
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int R = 16 / int(sizeof(T));
+    constexpr int G = 8 / R;  // vectors per group of 8 rows
+    const int lane = threadIdx.x;
+    const int m = P.m, C = P.C, ldm = P.ldm;
+    T *tab = P.tab;
+    const T p1e2 = lane_get(prow1, e2);
+    if (lane < C) {
+        V *col = reinterpret_cast<V *>(tab + lane * ldm);
+        const V *pc1 = reinterpret_cast<const V *>(tab + e1 * ldm);
+        const V *pc2 = reinterpret_cast<const V *>(tab + e2 * ldm);
+        const int nv = (m + R - 1) / R;
+        int k0 = 0;
+        for (; k0 + G <= nv; k0 += G) {
+            V v[G], w1[G], w2[G];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-        if (lane + 64 * r == l) P.basis[r] = ne;
-    if (lane == e) P.nonb = bl;
+            for (int g = 0; g < G; ++g) {
+                v[g] = col[k0 + g];
+                w1[g] = pc1[k0 + g];
+                w2[g] = pc2[k0 + g];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const T f2 = fma(-w1[g][q], p1e2, w2[g][q]);
+                    v[g][q] = fma(-f2, prow2, fma(-w1[g][q], prow1, v[g][q]));
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) col[k0 + g] = v[g];
+        }
+        for (; k0 < nv; ++k0) {
+            V v = col[k0];
+            const V w1 = pc1[k0], w2 = pc2[k0];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const T f2 = fma(-w1[q], p1e2, w2[q]);
+                v[q] = fma(-f2, prow2, fma(-w1[q], prow1, v[q]));
+            }
+            col[k0] = v;
+        }
+    }
+    // Columns e1 and e2 (row owners), then rows l1 and l2 (column owners).
+    const T pre1 = lane_get(prow1, e1), p2e1 = lane_get(prow2, e1), pre2 = lane_get(prow2, e2);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int i = lane + 64 * r;
+        if (i < m) {
+            const T c1 = (i == l1) ? pre1 : fma(-pcol1[r], pre1, T(0));
+            tab[e1 * ldm + i] = (i == l2) ? p2e1 : fma(-P.pcol[r], p2e1, c1);
+            tab[e2 * ldm + i] = (i == l2) ? pre2 : fma(-P.pcol[r], pre2, T(0));
+        }
+    }
+    if (lane < C && lane != e1 && lane != e2) {
+        if (l1 != l2) tab[lane * ldm + l1] = fma(-row_get<RB>(P.pcol, l1), prow2, prow1);
+        tab[lane * ldm + l2] = prow2;
+    }
 }
 
 // Loads column e into the per-row pivot-column registers (0 for dropped rows).
@@ -189,7 +286,10 @@ __device__ __forceinline__ int price(bool elig, T d, int nonb, bool bland)
     return __builtin_ctzll(__ballot(elig && nonb == bmin));
 }
 
-template <typename T, int RB>
+// PAIR: look one pivot ahead and sweep two pivots at once when it finds one
+// (off in the repair instantiation, whose few pivots do not pay for the
+// registers).
+template <typename T, int RB, bool PAIR = true>
 __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveParams &prm, int *enter)
 {
     const int lane = threadIdx.x;
@@ -266,8 +366,79 @@ __device__ __forceinline__ int simplex(WaveLP<T, RB> &P, T eps_opt, const SolveP
         }
         const int l = lane_get(row_loc, src);
         if (lane_get(th_loc, src) == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
-        pivot<T, RB>(P, l, e);
-        ++P.iters;
+        if (!PAIR || prm.pricing == 1 || P.iters + 1 >= P.cap) {
+            pivot<T, RB>(P, l, e);
+            ++P.iters;
+            continue;
+        }
+        // Look one pivot ahead: this pivot's register part (objective row,
+        // right-hand sides, indices) is all Steps 1 and 2 of the next
+        // iteration need, with the one column they read formed from its
+        // stored entries and this pivot's vectors.  When they find a second
+        // pivot both go through one sweep of the columns (pivot_sweep2).
+        T pcol1[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) pcol1[r] = P.pcol[r];
+        const T prow1 = pivot_head<T, RB>(P, l, e, (lane < P.C) ? tab[lane * ldm + l] : T(0));
+        const bool bland2 = prm.k_deg > 0 && deg_run >= prm.k_deg;
+        // Column e now holds the variable that left; its reduced cost -d_e / PE
+        // is negative, so e2 != e.
+        const int e2 = price<T>(lane < N && P.d > eps_opt && P.nonb < nm, P.d, P.nonb, bland2);
+        int l2 = -1;
+        T th2 = T(0);
+        if (e2 >= 0) {
+            const T p1e2 = lane_get(prow1, e2);
+            T th_loc2 = t_inf<T>();
+            int bb_loc2 = kBig, row_loc2 = -1;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int i = lane + 64 * r;
+                const bool live = !(P.rowf[r] & (kRowDead | kRowPad));
+                T a = T(0), bi = T(0);
+                if (i < m) {
+                    a = (i == l) ? p1e2 : fma(-pcol1[r], p1e2, tab[e2 * ldm + i]);
+                    bi = P.rhs[r];
+                }
+                P.pcol[r] = live ? a : T(0);
+                if (live && a > tol_piv) {
+                    const T th = (bi > T(0) ? bi : T(0)) / a;
+                    const int bb = P.basis[r];
+                    if (th < th_loc2 || (th == th_loc2 && bb < bb_loc2)) { th_loc2 = th; bb_loc2 = bb; row_loc2 = i; }
+                }
+            }
+            if (__ballot(row_loc2 >= 0)) {
+                const T best2 = wave_min_f(th_loc2);
+                const uint64_t tied2 = __ballot(row_loc2 >= 0 && th_loc2 == best2);
+                int src2;
+                if (__popcll(tied2) == 1) {
+                    src2 = __builtin_ctzll(tied2);
+                } else {
+                    const bool in = (tied2 >> lane) & 1;
+                    const int bmin = wave_min_i(in ? bb_loc2 : kBig);
+                    src2 = __builtin_ctzll(__ballot(in && bb_loc2 == bmin));
+                }
+                l2 = lane_get(row_loc2, src2);
+                th2 = lane_get(th_loc2, src2);
+            }
+        }
+        if (l2 < 0) {
+            // Optimal or unbounded after this pivot: it goes alone, and the
+            // next iteration reaches the same outcome.
+#pragma unroll
+            for (int r = 0; r < RB; ++r) P.pcol[r] = pcol1[r];
+            pivot_sweep<T, RB>(P, l, e, prow1);
+            ++P.iters;
+            continue;
+        }
+        if (th2 == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
+        // Lane j's entry of row l2 in the tableau the first pivot leaves.
+        T row2 = T(0);
+        if (lane < P.C)
+            row2 = (l2 == l) ? prow1
+                             : fma(-row_get<RB>(pcol1, l2), prow1, (lane == e) ? T(0) : tab[lane * ldm + l2]);
+        const T prow2 = pivot_head<T, RB>(P, l2, e2, row2);
+        pivot_sweep2<T, RB>(P, l, e, prow1, pcol1, l2, e2, prow2);
+        P.iters += 2;
     }
 }
 
@@ -385,7 +556,7 @@ __device__ int dual_repair(WaveLP<T, RB> &P, T eps_opt, T tol_dual, T tol_p, con
         for (int r = 0; r < RB; ++r)
             infeas |= lane + 64 * r < m && !(P.rowf[r] & (kRowDead | kRowPad)) && P.rhs[r] < -tol_p;
         if (__ballot(infeas)) return -1;
-        return simplex<T, RB>(P, eps_opt, prm, enter);
+        return simplex<T, RB, false>(P, eps_opt, prm, enter);
     }
     for (;;) {
         if (P.iters >= P.cap) return kIterLimit;
@@ -427,7 +598,7 @@ __device__ int dual_repair(WaveLP<T, RB> &P, T eps_opt, T tol_dual, T tol_p, con
         pivot<T, RB>(P, l, e);
         ++P.iters;
     }
-    return simplex<T, RB>(P, eps_opt, prm, enter);
+    return simplex<T, RB, false>(P, eps_opt, prm, enter);
 }
 
 // Bytes of LDS the wave kernel keeps in front of the tableau: the surplus
@@ -762,7 +933,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
                 P.z = zacc;
                 const double dmax = wave_max_f(lane < N ? fabs(double(acc)) : 0.0);
                 const double dscale = fmax(1.0, dmax);
-                const int r = simplex<T, RB>(P, T(a.prm.tol_opt * dscale), a.prm, &enter);
+                const int r = simplex<T, RB, !WARM>(P, T(a.prm.tol_opt * dscale), a.prm, &enter);
                 P.it1 = P.iters;
                 enter = -1;
                 if (r == kIterLimit) status = kIterLimit;
@@ -826,7 +997,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PFD > 0 ? 2 
                                                 T(a.prm.tol_feas * (1.0 + bnorm)), a.prm, &enter);
                     warm_defer = status != kOptimal;
                 } else {
-                    status = simplex<T, RB>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
+                    status = simplex<T, RB, !WARM>(P, T(a.prm.tol_opt * fmax(1.0, cnorm)), a.prm, &enter);
                 }
             }
         }
