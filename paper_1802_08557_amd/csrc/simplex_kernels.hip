@@ -143,14 +143,24 @@ __device__ __forceinline__ void pivot_vectors(LP<T, NT> &P, int l, int e)
         P.pcol[i] = (i < m && (P.rowf[i] & ROW_DEAD)) ? T(0) : tab[(int64_t)i * ld + e];
 }
 
-// Step 3's sweep for the pivot whose vectors are in P.prow / P.pcol: each
-// wavefront takes whole rows, every lane 16 bytes (R entries) per access and
-// U accesses in flight -- all loads, then the fmas, then all stores.  Rows
-// start 16-byte aligned (tableau_ld); the entries past C up to the row stride
-// are padding, updated with whatever they hold and never read back (the
-// pivot-row buffers are padded the same way).  No barrier.
-template <typename T, int NT>
-__device__ __forceinline__ void sweep1(LP<T, NT> &P, int l, int e)
+// Step 3's sweep: every tableau entry t_ij becomes fma(-pcol_i, prow_j, t_ij)
+// -- with 0 in place of t_ij in the pivot column e, and prow_j itself in the
+// pivot row l -- for the pivot whose vectors are in P.prow / P.pcol; with
+// PAIR, the result then takes the second pivot's rule the same way (vectors
+// in P.prow2 / P.pcol2, row l2, column e2).  Lanes move 16 bytes (R entries)
+// per access, U accesses in flight -- all loads, then the fmas, then all
+// stores.  Rows start 16-byte aligned (tableau_ld); the entries past C up to
+// the row stride are padding, updated with whatever they hold and never read
+// back (the pivot-row buffers are padded the same way).
+//   * Wide rows (more than 64 U / 2 vectors): each wavefront takes whole rows.
+//   * Narrow rows: each wavefront takes RW = 64 U / nv rows at a time, its
+//     lanes spread over those rows' vectors (item q = lane + 64 u is vector
+//     q % nv of row q / nv), so a narrow tableau still keeps every lane busy
+//     and many accesses in flight -- with a tableau in device memory the
+//     sweep is bound by the accesses in flight, not by the bytes.
+// No barrier.
+template <typename T, int NT, bool PAIR>
+__device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2, int e2)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int W = NT / 64;
@@ -160,37 +170,92 @@ __device__ __forceinline__ void sweep1(LP<T, NT> &P, int l, int e)
     constexpr int R = 16 / int(sizeof(T));
     constexpr int U = 4;
     const int nv = (C + R - 1) / R;
-    const V *pr = reinterpret_cast<const V *>(P.prow);
-    for (int i = wave; i <= m; i += W) {
-        V *row = reinterpret_cast<V *>(tab + (int64_t)i * ld);
-        if (i == l) {
-            for (int k = lane; k < nv; k += 64) row[k] = pr[k];
-            continue;
-        }
-        const T f = P.pcol[i];
-        for (int k0 = lane; k0 < nv; k0 += 64 * U) {
-            V v[U], w[U];
+    const V *pr1 = reinterpret_cast<const V *>(P.prow);
+    const V *pr2 = reinterpret_cast<const V *>(P.prow2);
+    // One entry's update: the first pivot's rule, then (PAIR) the second's.
+    auto upd = [&](int i, int j, T v, T w1, T f1, T w2, T f2) {
+        T t = (i == l1) ? w1 : fma(-f1, w1, (j == e1) ? T(0) : v);
+        if constexpr (PAIR) t = (i == l2) ? w2 : fma(-f2, w2, (j == e2) ? T(0) : t);
+        return t;
+    };
+    const int rw = (64 * U) / nv;  // rows per wavefront step on the narrow path
+    if (rw < 2) {
+        for (int i = wave; i <= m; i += W) {
+            V *row = reinterpret_cast<V *>(tab + (int64_t)i * ld);
+            const T f1 = P.pcol[i];
+            const T f2 = PAIR ? P.pcol2[i] : T(0);
+            for (int k0 = lane; k0 < nv; k0 += 64 * U) {
+                V v[U], w1[U], w2[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + 64 * u;
-                if (k < nv) { v[u] = row[k]; w[u] = pr[k]; }
-            }
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + 64 * u;
+                    if (k < nv) {
+                        v[u] = row[k];
+                        w1[u] = pr1[k];
+                        if constexpr (PAIR) w2[u] = pr2[k];
+                    }
+                }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + 64 * u;
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + 64 * u;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T base = (k * R + r == e) ? T(0) : v[u][r];
-                    v[u][r] = fma(-f, w[u][r], base);
+                    for (int r = 0; r < R; ++r)
+                        v[u][r] = upd(i, k * R + r, v[u][r], w1[u][r], f1, PAIR ? w2[u][r] : T(0), f2);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + 64 * u;
+                    if (k < nv) row[k] = v[u];
                 }
             }
+        }
+        return;
+    }
+    // Narrow rows: this lane's items, as (row offset, vector) pairs.
+    int ro[U], kv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + 64 * u;
-                if (k < nv) row[k] = v[u];
+    for (int u = 0; u < U; ++u) {
+        const int q = lane + 64 * u;
+        ro[u] = q / nv;
+        kv[u] = q - ro[u] * nv;
+        if (ro[u] >= rw) ro[u] = m + 1;  // past the last row: no item
+    }
+    for (int i0 = wave * rw; i0 <= m; i0 += W * rw) {
+        V v[U], w1[U], w2[U];
+        T f1[U], f2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + ro[u];
+            if (i <= m) {
+                v[u] = reinterpret_cast<const V *>(tab + (int64_t)i * ld)[kv[u]];
+                w1[u] = pr1[kv[u]];
+                f1[u] = P.pcol[i];
+                if constexpr (PAIR) {
+                    w2[u] = pr2[kv[u]];
+                    f2[u] = P.pcol2[i];
+                }
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + ro[u];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[u][r] = upd(i, kv[u] * R + r, v[u][r], w1[u][r], f1[u], PAIR ? w2[u][r] : T(0),
+                              PAIR ? f2[u] : T(0));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + ro[u];
+            if (i <= m) reinterpret_cast<V *>(tab + (int64_t)i * ld)[kv[u]] = v[u];
+        }
     }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void sweep1(LP<T, NT> &P, int l, int e)
+{
+    sweep_impl<T, NT, false>(P, l, e, -1, -1);
 }
 
 // Step 3: pivot on (l, e).  Every thread takes part; ends with a barrier.
@@ -219,52 +284,7 @@ __device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
 template <typename T, int NT>
 __device__ __forceinline__ void sweep2(LP<T, NT> &P, int l1, int e1, int l2, int e2)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int W = NT / 64;
-    T *tab = P.tab;
-    const int ld = P.ld, C = P.C, m = P.m;
-    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int R = 16 / int(sizeof(T));
-    constexpr int U = 4;
-    const int nv = (C + R - 1) / R;
-    const V *pr1 = reinterpret_cast<const V *>(P.prow);
-    const V *pr2 = reinterpret_cast<const V *>(P.prow2);
-    for (int i = wave; i <= m; i += W) {
-        V *row = reinterpret_cast<V *>(tab + (int64_t)i * ld);
-        if (i == l2) {
-            for (int k = lane; k < nv; k += 64) row[k] = pr2[k];
-            continue;
-        }
-        const bool first = i == l1;
-        const T f1 = P.pcol[i], f2 = P.pcol2[i];
-        for (int k0 = lane; k0 < nv; k0 += 64 * U) {
-            V v[U], w1[U], w2[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + 64 * u;
-                if (k < nv) {
-                    if (!first) v[u] = row[k];
-                    w1[u] = pr1[k];
-                    w2[u] = pr2[k];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + 64 * u;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int j = k * R + r;
-                    T t = first ? w1[u][r] : fma(-f1, w1[u][r], (j == e1) ? T(0) : v[u][r]);
-                    v[u][r] = fma(-f2, w2[u][r], (j == e2) ? T(0) : t);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + 64 * u;
-                if (k < nv) row[k] = v[u];
-            }
-        }
-    }
+    sweep_impl<T, NT, true>(P, l1, e1, l2, e2);
 }
 
 // Steps 1-3 until a halt condition.  Returns ST_OPTIMAL, ST_UNBOUNDED or ST_ITER;
@@ -496,7 +516,7 @@ __device__ __forceinline__ void price_out(LP<T, NT> &P)
 // on its tight rows or a pivot entry falls below tol_piv.  P.colrow (unused
 // without surplus columns) holds the tight-row flags.
 template <typename T, int NT>
-__device__ bool crash(LP<T, NT> &P, const SolveArgs &a)
+__device__ __forceinline__ bool crash(LP<T, NT> &P, const SolveArgs &a)
 {
     const int tid = threadIdx.x;
     const int m = P.m, n = P.n, N = P.N, ld = P.ld;
@@ -557,7 +577,7 @@ __device__ bool crash(LP<T, NT> &P, const SolveArgs &a)
 // feasible goes straight to the primal method.  Returns the status, or -1
 // when the start is neither.
 template <typename T, int NT>
-__device__ int dual_repair(LP<T, NT> &P, T eps_opt, T tol_dual, T tol_p, const SolveParams &prm, int *enter)
+__device__ __forceinline__ int dual_repair(LP<T, NT> &P, T eps_opt, T tol_dual, T tol_p, const SolveParams &prm, int *enter)
 {
     const int tid = threadIdx.x;
     const int m = P.m, N = P.N, ld = P.ld, nm = P.n + P.m;
