@@ -22,10 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published figures: 256 CUs at 2.4 GHz; HBM3E 8 TB/s.  LDS: 128 B/clk
-# per CU is the CDNA3-class figure (78.6 TB/s); the denominator of the LDS
-# roofline is the larger of it and the rates measured on the device itself
-# (lp_measure_peaks: 16-byte reads, and 16-byte read-then-write as in the
-# pivot sweep), so a higher CDNA4 rate is never missed.
+# per CU is the CDNA3-class figure (78.6 TB/s), reported for reference; the
+# denominator of the LDS roofline is the rate measured on the device itself
+# for the pivot sweep's access mix (lp_measure_peaks: 16-byte reads each
+# followed by a 16-byte write), used whenever the measurement ran.
 N_CU, CLOCK_HZ = 256, 2.4e9
 PEAK_HBM = 8.0e12
 LDS_NOMINAL = N_CU * 128 * CLOCK_HZ  # 78.6 TB/s
@@ -83,10 +83,22 @@ def algorithmic_bytes(batch, stats, tsize):
 def roofline(per_kernel, dom, lds_bytes, hbm_bytes, peaks, workload_name):
     """Roofline of the dominant solve kernel: the busier memory tier for the
     algorithmic bytes, T = max(LDS bytes / LDS peak, HBM bytes / HBM peak),
-    against the kernel's measured time per solve.  The LDS peak is the larger
-    of the nominal 128 B/clk/CU and the device's measured rates; frac is also
-    given against the nominal figure alone."""
-    lds_peak = max([LDS_NOMINAL] + [peaks.get(k, 0.0) for k in ("lds_read", "lds_read_write")])
+    against the kernel's measured time per solve.
+
+    The algorithmic LDS bytes of a pivot are one read and one write of the
+    tableau (plus one write to build it), so the LDS peak is the rate the
+    device itself reaches on that mix: 16-byte reads each followed by a
+    16-byte write (lp_measure_peaks' read+write stream).  Reads alone run at
+    about 2.5x the rate of writes alone on gfx950, so the read-only rate
+    overstates what a half-write stream can reach; frac is also given
+    against it and against the nominal 128 B/clk/CU.  The HBM peak is the
+    published 8 TB/s (a device copy reaches hbm_copy).  traffic: measured
+    HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated), null when
+    the kernel sources changed since the counters were taken; lds_traffic:
+    the same from the LDS bandwidth counters."""
+    lds_mix = peaks.get("lds_read_write", 0.0)
+    lds_peak = lds_mix if lds_mix > 0 else LDS_NOMINAL
+    lds_read = peaks.get("lds_read", 0.0)
     dom_s = per_kernel[dom] * 1e-3
     if lds_bytes / lds_peak >= hbm_bytes / PEAK_HBM:
         roof = dict(bound="lds", achieved=lds_bytes / dom_s / 1e9, peak=lds_peak / 1e9, unit="GB/s",
@@ -97,9 +109,16 @@ def roofline(per_kernel, dom, lds_bytes, hbm_bytes, peaks, workload_name):
     tr = measured_traffic(dom, workload_name)
     roof["traffic"] = tr["hbm"] if tr else None
     roof.update(kernel=dom, kernel_ms=per_kernel[dom], lds_bytes_alg=lds_bytes, hbm_bytes_alg=hbm_bytes,
-                lds_frac=lds_bytes / dom_s / lds_peak, lds_frac_vs_nominal=lds_bytes / dom_s / LDS_NOMINAL,
+                lds_peak_basis="measured 16-byte read+write" if lds_mix > 0 else "nominal 128 B/clk/CU",
+                lds_frac=lds_bytes / dom_s / lds_peak,
+                lds_frac_vs_read_peak=lds_bytes / dom_s / lds_read if lds_read > 0 else None,
+                lds_frac_vs_nominal=lds_bytes / dom_s / LDS_NOMINAL,
                 hbm_frac=hbm_bytes / dom_s / PEAK_HBM,
                 lds_traffic=tr["lds"] if tr else None)
+    if tr and tr["hbm"]:
+        # Measured bytes over the same time: below the algorithmic figure when
+        # pivots are swept in pairs (one pass of the tableau for two pivots).
+        roof.update(traffic_gb_per_s=tr["hbm"] / dom_s / 1e9, traffic_frac=tr["hbm"] / dom_s / PEAK_HBM)
     return roof
 
 
