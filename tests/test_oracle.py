@@ -344,3 +344,43 @@ def test_steepest_edge_reaches_the_brute_force_optimum(seed):
         assert r.status[0] == st
         if st == oracle.OPTIMAL:
             assert r.obj[0] == pytest.approx(z, rel=1e-9, abs=1e-9)
+
+
+# ---------------------------------------------------------------- Phase I drive-out and redundant rows
+
+def test_redundant_equality_row_is_dropped():
+    # max x1 + x2  s.t.  x1 + x2 = 2,  2 x1 + 2 x2 = 4 (twice the first row),  x1 <= 1.5.
+    # Both equalities get artificials; Phase I ends at w* = 0 with one artificial
+    # still basic at zero in a row whose non-artificial entries are all zero
+    # after the other equality's pivot: that row is redundant and is dropped
+    # (basis -1).  The optimum is z = 2 (any split of x1 + x2 = 2 with x1 <= 1.5).
+    A = np.array([[1.0, 1.0], [2.0, 2.0], [1.0, 0.0]])
+    b = np.array([2.0, 4.0, 1.5])
+    c = np.array([1.0, 1.0])
+    s = np.array([oracle.EQ, oracle.EQ, oracle.LE], np.int8)
+    r = oracle.solve_one(A, b, c, s)
+    assert r.status[0] == oracle.OPTIMAL
+    assert r.obj[0] == pytest.approx(2.0, abs=1e-12)
+    assert np.sum(r.basis == -1) == 1
+    n, m = 2, 3
+    assert not np.any(r.basis >= n + m)  # no artificial left in the basis
+    assert brute_force(A, b, c, s) == (oracle.OPTIMAL, pytest.approx(2.0, abs=1e-9))
+    cert = certificate(A, b, c, s, r.basis, r.x)
+    assert cert["ok"], cert
+
+
+def test_artificial_at_zero_is_driven_out_not_dropped():
+    # max x1 + 2 x2  s.t.  x1 - x2 = 0,  x1 + x2 <= 4.  Row 0 has b = 0: its
+    # artificial is basic at zero from the start, Phase I is optimal at once,
+    # and the drive-out pivots x1 (the smallest-index column with a non-zero
+    # entry in that row) into it; nothing is dropped.  Optimum x = (2, 2), z = 6.
+    A = np.array([[1.0, -1.0], [1.0, 1.0]])
+    b = np.array([0.0, 4.0])
+    c = np.array([1.0, 2.0])
+    s = np.array([oracle.EQ, oracle.LE], np.int8)
+    r = oracle.solve_one(A, b, c, s)
+    assert r.status[0] == oracle.OPTIMAL
+    assert r.obj[0] == pytest.approx(6.0, abs=1e-12)
+    np.testing.assert_allclose(r.x, [2.0, 2.0], atol=1e-12)
+    assert np.all(r.basis >= 0) and not np.any(r.basis >= 4)
+    assert brute_force(A, b, c, s) == (oracle.OPTIMAL, pytest.approx(6.0, abs=1e-9))
