@@ -183,6 +183,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
             double rz = 0.0, cs = 0.0;
             int pos = kBig;  // step at which this lane's row became the pivot row
             int ordr = 0;    // lane p: the row chosen at step p
+            double rinv = 0.0;  // lane p: 1 / U_pp, recorded by the LU's step p
             const double btl = __shfl(bi, tl), csl = __shfl(cj, sl);
             if (ok) {
                 double am = 0.0;
@@ -210,13 +211,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
                 dsync();
                 for (int p = 0; p < K; ++p) {
                     const double vp = (lane < K && pos == kBig) ? fabs(colv) : -1.0;
+                    // Every lane's reciprocal, computed while the maximum is
+                    // reduced: the pivot's is taken below, off the serial chain.
+                    const double cinv = 1.0 / colv;
                     const double vmax = wave_max_f(vp);
                     if (!(vmax > 1e-13 * fmax(1.0, amax))) { ok = false; break; }
                     const int pl = __builtin_ctzll(__ballot(vp == vmax));
                     if (lane == pl) pos = p;
                     if (lane == p) ordr = pl;
                     if (lane == 0) order[p] = pl;
-                    const double uinv = 1.0 / lane_get(colv, pl);
+                    const double uinv = lane_get(cinv, pl);
+                    if (lane == p) rinv = uinv;
                     const bool act = lane < K && pos == kBig;
                     const int la = act ? lane : pl;
                     const double l = colv * uinv;
@@ -247,8 +252,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
             double xr = 0.0;  // lane p: x of the p-th basic structural
             if (ok) {
                 // x_S (L z = P b_T, then U x = z) and y_T (U^T w = c_S, then
-                // L^T v = w, y_t = v[pos_t]) side by side; lane p keeps 1 / U_pp.
-                double rinv = 0.0, wr = 0.0;
+                // L^T v = w, y_t = v[pos_t]) side by side; 1 / U_pp comes from the LU (lane p).
+                double wr = 0.0;
                 for (int p0 = 0; p0 < K; p0 += CG) {
                     double mv[CG] = {}, mu[CG] = {};
                     int op[CG];
@@ -268,9 +273,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
                         if (p < K) {
                             const double zp = lane_get(rz, lane_get(ordr, p));
                             if (lane < K && pos > p) rz = fma(-mv[q], zp, rz);
-                            const double ip = 1.0 / lane_get(mu[q], p);
-                            if (lane == p) rinv = ip;
-                            const double wp = lane_get(cs, p) * ip;
+                            const double wp = lane_get(cs, p) * lane_get(rinv, p);
                             if (lane == p) wr = wp;
                             if (lane > p && lane < K) cs = fma(-mu[q], wp, cs);
                         }
