@@ -9,6 +9,8 @@ Contents
                       batch, multithreaded over LPs (paper Sec. 4 / 4.1).
   * ``brute``      -- vertex enumeration for tiny LPs (an independent check).
   * ``certificate``-- KKT / strong-duality check of an optimal basis.
+  * ``phase1_certificate`` -- the same for a Phase I basis that proves an LP
+                      infeasible (Phase I optimum below zero; Farkas).
   * ``hyperbox``   -- the closed-form box LP of Eq. (7), Sec. 5.6.
   * ``scaling``    -- power-of-two geometric-mean scaling (not in the paper;
                       the reference for the optional preconditioning).
@@ -149,5 +151,5 @@ def solve_one(A, b, c, sense=None, **kw) -> Result:
     return solve(A.ravel(), b, c, sense, [m], [n], **kw)
 
 
-from .brute import brute_force, certificate  # noqa: E402
+from .brute import brute_force, certificate, phase1_certificate  # noqa: E402
 from .hyperbox import hyperbox_max  # noqa: E402

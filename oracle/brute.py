@@ -160,3 +160,55 @@ def certificate(A, b, c, sense, basis, x, tol=1e-7):
     ok = (primal <= tol * bscale * (1 + np.abs(xfull).max()) and dual <= tol * cscale
           and gap <= tol * zscale and xdiff <= tol * (1 + np.abs(xfull).max()))
     return dict(ok=bool(ok), primal=primal, dual=dual, gap=gap, xdiff=xdiff, x=xfull, y=y)
+
+
+def phase1_certificate(A, b, sense, basis, tol=1e-9):
+    """Check that ``basis`` (Bland indices as in ``certificate``) is an optimal
+    basis of the Phase I problem -- max -(sum of artificials) over the
+    normalised slack form with one artificial per >= and = row (the paper's
+    Sec. 4 start) -- whose optimum is negative, i.e. that it proves the LP
+    infeasible.  Everything is recomputed from A and b in float64.
+
+    x_B = B^-1 b must be >= 0 (Phase I primal feasibility), y = B^-T c_B with
+    c = -1 on artificials and 0 elsewhere must leave the reduced cost
+    c_k - y^T a_k <= 0 of every structural and slack / surplus column, and
+    w* = c_B^T x_B = b^T y must lie below -tol (1 + |b|_inf).  Then -y is a
+    Farkas certificate: -y^T a_j <= 0 for every column of the LP itself and
+    -y^T b > 0, so no x >= 0 satisfies the constraints.  Artificial columns
+    are not checked: they are not part of the LP, and the method never
+    prices an artificial again once it has left the basis.  Returns a dict
+    with ``ok``, ``w``, ``primal`` (largest negative x_B), ``dual`` (largest
+    reduced cost) and ``y``."""
+    A = np.asarray(A, float)
+    m, n = A.shape
+    b = np.asarray(b, float).copy()
+    sense = np.asarray(sense, int).copy()
+    sgn = np.where(b < 0, -1.0, 1.0)
+    flip = (b < 0) & (sense != EQ)
+    sense[flip] = np.where(sense[flip] == LE, GE, LE)
+    An = A * sgn[:, None]
+    bn = b * sgn
+    cols, cost = {}, {}
+    for j in range(n):
+        cols[j], cost[j] = An[:, j], 0.0
+    for i in range(m):
+        if sense[i] != EQ:
+            v = np.zeros(m); v[i] = 1.0 if sense[i] == LE else -1.0
+            cols[n + i], cost[n + i] = v, 0.0
+        if sense[i] != LE:
+            v = np.zeros(m); v[i] = 1.0
+            cols[n + m + i], cost[n + m + i] = v, -1.0
+    Bidx = [int(k) for k in basis]
+    if len(Bidx) != m or any(k not in cols for k in Bidx) or len(set(Bidx)) != m:
+        return dict(ok=False, w=float("nan"), primal=float("inf"), dual=float("inf"), y=None)
+    B = np.stack([cols[k] for k in Bidx], axis=1)
+    cB = np.array([cost[k] for k in Bidx])
+    xB = np.linalg.solve(B, bn)
+    y = np.linalg.solve(B.T, cB)
+    w = float(cB @ xB)
+    primal = float(max(0.0, -xB.min()))
+    basic = set(Bidx)
+    dual = max([cost[k] - float(y @ col) for k, col in cols.items() if k not in basic and k < n + m] + [0.0])
+    scale = 1.0 + np.abs(b).max()
+    ok = primal <= tol * scale and dual <= tol * max(1.0, np.abs(An).sum(axis=0).max()) and w < -tol * scale
+    return dict(ok=bool(ok), w=w, primal=primal, dual=dual, y=y)

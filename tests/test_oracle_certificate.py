@@ -83,3 +83,92 @@ def test_negative_rhs_row_is_normalised():
     cert = certificate(A2, b2, c, np.array([1, 0, 0], np.int8), [0, 1, N + 2], [3.0, 1.0])
     assert cert["ok"]
     np.testing.assert_allclose(cert["y"], [1.5, 0.5, 0.0], atol=1e-14)
+
+
+# ---------------------------------------------------------------- Phase I (infeasibility)
+
+from oracle import phase1_certificate  # noqa: E402
+import oracle  # noqa: E402
+
+# x1 + x2 <= 4 and x1 + x2 >= 6.  By hand: Phase I starts with the slack of
+# row 0 and the artificial of row 1 (index n + m + 1 = 5) basic; x1 enters
+# (reduced cost 1, the smaller index of a tie), row 0 leaves (ratio 4 < 6), and
+# then every reduced cost is <= 0 with a1 = 2: w* = -2.  Duals of the final
+# basis {x1, a1}: y = (1, -1); -y = (-1, 1) is a Farkas certificate
+# (-y^T A = (0, 0), -y^T b = 2 > 0).
+A2 = np.array([[1.0, 1.0], [1.0, 1.0]])
+b2 = np.array([4.0, 6.0])
+s2 = np.array([0, 1], np.int8)
+
+
+def test_phase1_hand_worked_basis_and_duals():
+    r = oracle.solve_one(A2, b2, np.array([1.0, 1.0]), s2)
+    assert r.status[0] == oracle.INFEASIBLE
+    assert list(r.basis) == [0, 5]
+    cert = phase1_certificate(A2, b2, s2, [0, 5])
+    assert cert["ok"]
+    assert cert["w"] == pytest.approx(-2.0)
+    np.testing.assert_allclose(cert["y"], [1.0, -1.0], atol=1e-14)
+
+
+def test_phase1_single_negative_row():
+    # x1 + x2 <= -1 is -x1 - x2 >= 1 after normalisation: its artificial stays
+    # basic (index n + m = 3) at 1, every reduced cost is -1: w* = -1, y = -1.
+    A = np.array([[1.0, 1.0]])
+    cert = phase1_certificate(A, [-1.0], [0], [3])
+    assert cert["ok"] and cert["w"] == pytest.approx(-1.0)
+    np.testing.assert_allclose(cert["y"], [-1.0])
+
+
+def test_phase1_rejects_non_optimal_and_feasible():
+    # The starting basis {s0, a1} of the hand example: x1's reduced cost is 1.
+    cert = phase1_certificate(A2, b2, s2, [2, 5])
+    assert not cert["ok"] and cert["dual"] == pytest.approx(1.0)
+    # A feasible LP's optimal Phase I basis has w* = 0: no proof of infeasibility.
+    A = np.array([[1.0, 1.0], [1.0, 1.0]])
+    b = np.array([6.0, 4.0])
+    s = np.array([0, 1], np.int8)  # x1 + x2 <= 6, x1 + x2 >= 4: feasible
+    cert = phase1_certificate(A, b, s, [2, 0])  # slack of row 0 (index n + 0), x1 in row 1
+    assert not cert["ok"] and cert["w"] == pytest.approx(0.0)
+    # Not a basis of this LP (a repeated index).
+    assert not phase1_certificate(A2, b2, s2, [0, 0])["ok"]
+
+
+def test_phase1_oracle_bases_of_infeasible_lps_pass():
+    # Brute force decides infeasibility of small random LPs of every sense;
+    # the oracle's final Phase I basis of each infeasible one must prove it.
+    rng = np.random.default_rng(5)
+    seen = 0
+    for _ in range(300):
+        m, n = rng.integers(2, 5), rng.integers(2, 5)
+        A = rng.integers(-4, 5, size=(m, n)).astype(float)
+        b = rng.integers(-6, 7, size=m).astype(float)
+        s = rng.integers(0, 3, size=m).astype(np.int8)
+        st, _ = oracle.brute_force(A, b, np.ones(n), s)
+        if st != oracle.INFEASIBLE:
+            continue
+        r = oracle.solve_one(A, b, np.ones(n), s)
+        assert r.status[0] == oracle.INFEASIBLE
+        assert phase1_certificate(A, b, s, r.basis)["ok"], (A, b, s, r.basis)
+        seen += 1
+    assert seen > 30
+
+
+def test_phase1_oracle_bases_of_injected_infeasible_lps_pass():
+    # The uneven workload's injected infeasible LPs (a row x1 + x2 <= -1
+    # appended to Gaussian LPs with >= rows): every one is proven infeasible
+    # by the oracle's final Phase I basis; a feasible LP's basis proves nothing.
+    from paper_1802_08557_amd import workloads as W
+    bt = W.uneven_batch(400, seed=31, lo=10, hi=40)
+    ref = oracle.solve(bt.A, bt.b, bt.c, bt.sense, bt.m, bt.n, threads=4)
+    aoff, roff, coff = bt.offsets()
+    inf = [int(k) for k in bt.meta["infeasible"]]
+    assert len(inf) >= 10
+    for k in inf:
+        A, b, c, s = bt.lp(k)
+        assert ref.status[k] == oracle.INFEASIBLE
+        assert phase1_certificate(A, b, s, ref.basis[roff[k]:roff[k + 1]])["ok"], k
+    opt = [k for k in range(bt.num_lps) if ref.status[k] == oracle.OPTIMAL][:20]
+    for k in opt:
+        A, b, c, s = bt.lp(k)
+        assert not phase1_certificate(A, b, s, ref.basis[roff[k]:roff[k + 1]])["ok"], k
