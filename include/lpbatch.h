@@ -90,6 +90,12 @@ typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32_CERT64 = 1 } lp_precision;
 #define LP_CERT_DUAL_OK 2
 #define LP_CERT_RAY_OK 4
 #define LP_CERT_SINGULAR 8
+/* An infeasible result proven in FP64 from the FP32 solve's final Phase I
+ * basis (Phase I optimum below zero, every structural and slack reduced cost
+ * within tolerance: -y is a Farkas certificate).  Given by the workgroup
+ * certificate (LPs with their own constraints and more than 64 rows and
+ * columns); other infeasible results are re-solved in FP64. */
+#define LP_CERT_INFEASIBLE_OK 16
 
 #define LP_PLACE_LDS 1    /* tableau in LDS (stats: one wavefront per LP)    */
 #define LP_PLACE_HBM 2    /* tableau in a device-memory slot (workgroup)     */

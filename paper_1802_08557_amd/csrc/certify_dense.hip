@@ -143,6 +143,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
             const bool neg = bi < 0.0;
             if (neg && sen != kEQ) sen = (sen == kLE) ? kGE : kLE;
             if (lane < m) rowfl[lane] = (neg ? kRowNeg : 0) | (sen << 1) | kTightD;
+            // x = 0 feasible (every normalised row <= or b = 0): a ray alone
+            // then proves the LP unbounded.
+            const bool origin = !__ballot(lane < m && sen != kLE && bi != 0.0);
             if (lane < n) colfl[lane] = 0;
             dsync();
             if (lane < m) {
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
                         else if (rs == kGE) df &= yt <= tol_d;
                     }
                     if (dall(df)) cert |= LP_CERT_DUAL_OK_BIT;
-                } else if (st0 == kUnbounded && primal_ok) {
+                } else if (st0 == kUnbounded && (primal_ok || origin)) {
                     // Ray of the entering variable q: w = B^-1 a_q, d_S = -w.
                     const int q = enter_q;
                     const bool qbasic = q >= 0 && q < n && __shfl(spos, q) >= 0;

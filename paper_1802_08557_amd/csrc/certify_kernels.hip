@@ -13,9 +13,20 @@
 //     non-basic structural j, and for the logical of every tight row:
 //     -y_i <= tol (slack, <= row) or y_i <= tol (surplus, >= row).
 //     Together these give c^T x = b^T y, i.e. optimality (strong duality).
-//   * For an LP reported unbounded with entering variable q: the basis must
-//     pass the primal certificate and the ray (x_q = t, x_S = x_S - t B^-1 a_q)
-//     must keep every basic variable non-negative and raise the objective.
+//   * For an LP reported unbounded with entering variable q: the ray
+//     (x_q = t, x_S = x_S - t B^-1 a_q) must keep every basic variable and
+//     every row's slack non-decreasing where it must stay non-negative and
+//     raise the objective, and the LP must have a feasible point: the basis
+//     passes the primal certificate, or x = 0 is feasible (every normalised
+//     row is <= or has b = 0), as for LPs whose rows are all <= with b >= 0.
+//   * For an LP reported infeasible (workgroup kernel, LPs with their own
+//     constraints): the final basis is the Phase I basis (artificial cost -1,
+//     rows R whose artificial is basic).  x_S = B_TS^-1 b_T, every artificial
+//     and slack value >= -tol, y_T = B_TS^-T (sum over R of the rows' entries
+//     in S), y = -1 on R; every structural and slack / surplus reduced cost
+//     <= tol (artificials are not priced again once they left); and the Phase
+//     I optimum w* = -(sum of the artificial values) below -tol.  -y is then
+//     a Farkas certificate of infeasibility.
 // An LP whose result passes is written with its FP64 x and objective; any
 // other LP (failed certificate, singular block, or a status other than
 // optimal / unbounded / invalid input) is appended to the fallback list and
@@ -28,7 +39,7 @@
 namespace lpb {
 namespace {
 
-constexpr int kTight = 32, kDeadRow = 64;
+constexpr int kTight = 32, kDeadRow = 64, kArtRow = 128;
 
 template <int NT>
 struct CertCtrl {
@@ -156,11 +167,15 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
         const int64_t mat_off = align16(sizeof(CertCtrl<NT>)) + align16(4 * int64_t(3 * m + 3 * n)) +
                                 align16(8 * 3 * int64_t(kmax) + 4 * int64_t(kmax));
         int cert = 0;
-        bool fallback = !(st0 == kOptimal || st0 == kUnbounded);
+        // An infeasible result of an LP's own constraints: the Phase I
+        // certificate (a screened relaxation's goes to the re-solve).
+        const bool phase1 = st0 == kInfeasible && !sub;
+        bool fallback = !(st0 == kOptimal || st0 == kUnbounded || phase1);
         // Invalid input stays invalid -- unless it was only the screening's row
         // list that was bad: the re-solve on all rows then decides.
         if (st0 == kInvalid) fallback = a.shared && a.row_subset;
-        const bool work = st0 == kOptimal || st0 == kUnbounded;
+        const bool work = st0 == kOptimal || st0 == kUnbounded || phase1;
+        bool origin_out = false;  // this thread's rows: is x = 0 outside the feasible set?
 
         if (work) {
             // Rows: sign normalisation, and which rows are tight.
@@ -171,6 +186,7 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                 const bool neg = bi < 0.0;
                 if (neg && sen != kEQ) sen = (sen == kLE) ? kGE : kLE;
                 rowf[i] = (neg ? kRowNeg : 0) | (sen << 1) | (sub ? 0 : kTight);
+                origin_out |= sen != kLE && bi != 0.0;
             }
             for (int j = tid; j < n; j += NT) colf[j] = 0;
             __syncthreads();
@@ -204,9 +220,11 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     if (q < 0) { sh->fail = 9; continue; }
                     atomicAnd(&rowf[q], ~kTight);
                 } else {
+                    // A basic artificial: a redundant row at an optimum, a row
+                    // of the Phase I objective at an infeasible end.
                     const int q = full_row(v - n - ms);
                     if (q < 0) { sh->fail = 9; continue; }
-                    atomicOr(&rowf[q], kDeadRow);
+                    atomicOr(&rowf[q], phase1 ? kArtRow : kDeadRow);
                     atomicAnd(&rowf[q], ~kTight);
                 }
             }
@@ -240,7 +258,18 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                 for (int t = tid; t < K; t += NT) {
                     const int i = tlist[t];
                     xs[t] = ((rowf[i] & kRowNeg) ? -1.0 : 1.0) * b[i];
-                    yt[t] = c[slist[t]];
+                    double ct = 0.0;
+                    if (phase1) {
+                        // c_S = 0 and y = -1 on the artificials' rows R:
+                        // B_TS^T y_T = sum over R of the rows' entries in S.
+                        const int jc = slist[t];
+                        for (int r2 = 0; r2 < m; ++r2)
+                            if (rowf[r2] & kArtRow)
+                                ct += ((rowf[r2] & kRowNeg) ? -1.0 : 1.0) * A[int64_t(r2) * n + jc];
+                    } else {
+                        ct = c[slist[t]];
+                    }
+                    yt[t] = ct;
                     perm[t] = t;
                 }
                 double am = 0.0;
@@ -316,6 +345,7 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
 
                 // Primal certificate.
                 bool pf = true;
+                double art = 0.0;  // Phase I: this thread's artificial values
                 for (int s2 = tid; s2 < K; s2 += NT) pf &= xs[s2] >= -tol_p;
                 for (int i = tid; i < m; i += NT) {
                     const int f = rowf[i];
@@ -325,7 +355,8 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     for (int s2 = 0; s2 < K; ++s2) ax = fma(A[int64_t(i) * n + slist[s2]], xs[s2], ax);
                     const double r = sg * (b[i] - ax);  // normalised slack b_i - a_i x
                     const int sen = (f >> 1) & 3;
-                    if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;  // a row left out of a screened solve can be an equality
+                    if (f & kArtRow) { pf &= r >= -tol_p; art += r; }  // the row's artificial value
+                    else if ((f & kDeadRow) || sen == kEQ) pf &= fabs(r) <= tol_p;  // a row left out of a screened solve can be an equality
                     else if (sen == kLE) pf &= r >= -tol_p;
                     else if (sen == kGE) pf &= -r >= -tol_p;
                 }
@@ -335,6 +366,52 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                 if (primal_ok) cert |= LP_CERT_PRIMAL_OK_BIT;
                 __syncthreads();
 
+                if (phase1 && primal_ok) {
+                    // Phase I optimum w* = -(sum of the artificial values), the
+                    // largest reduced cost 0 - y^T a_j over the non-basic
+                    // structurals (y = y_T on T, -1 on R) and the scale of
+                    // Phase I's first objective row (the sums over the >= and
+                    // = rows), each reduced over the workgroup.
+                    double worst = -1.0, dmax = 1.0;
+                    for (int j = tid; j < n; j += NT) {
+                        double start = 0.0, onr = 0.0;
+                        for (int i = 0; i < m; ++i) {
+                            const int f = rowf[i];
+                            const double v = ((f & kRowNeg) ? -1.0 : 1.0) * A[int64_t(i) * n + j];
+                            if (((f >> 1) & 3) != kLE) start += v;
+                            if (f & kArtRow) onr += v;
+                        }
+                        dmax = fmax(dmax, fabs(start));
+                        if (spos[j] >= 0) continue;
+                        double ya = 0.0;
+                        for (int t = 0; t < K; ++t) {
+                            const int i = tlist[t];
+                            const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
+                            ya = fma(yt[t], sg * A[int64_t(i) * n + j], ya);
+                        }
+                        worst = fmax(worst, onr - ya);  // -(y_T^T a_Tj - a_Rj)
+                    }
+                    // Slacks / surpluses of the tight rows (cost 0): -sigma_i y_i.
+                    for (int t = tid; t < K; t += NT) {
+                        const int sen = (rowf[tlist[t]] >> 1) & 3;
+                        if (sen == kLE) worst = fmax(worst, -yt[t]);
+                        else if (sen == kGE) worst = fmax(worst, yt[t]);
+                    }
+                    double wsum = art;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+                    if constexpr (NT > 64) {
+                        if (lane == 0) sh->rd[wave] = wsum;
+                        __syncthreads();
+                        wsum = 0.0;
+                        for (int qq = 0; qq < NT / 64; ++qq) wsum += sh->rd[qq];
+                        __syncthreads();
+                    }
+                    worst = blk_max<NT>(worst, sh);
+                    dmax = blk_max<NT>(dmax, sh);
+                    const double wstar = -wsum;
+                    if (worst <= a.tol_opt * dmax && wstar < -tol_p) cert |= LP_CERT_INFEASIBLE_OK_BIT;
+                }
                 if (st0 == kOptimal && primal_ok) {
                     // Dual certificate: reduced costs of every non-basic column.
                     bool df = true;
@@ -356,8 +433,15 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     if (!df) sh->fail = 2;
                     __syncthreads();
                     if (sh->fail == 0) cert |= LP_CERT_DUAL_OK_BIT;
-                } else if (st0 == kUnbounded && primal_ok) {
+                }
+                // x = 0 is feasible when every normalised row is <= (b >= 0) or
+                // has b = 0: then a ray alone proves the LP unbounded, whatever
+                // the FP64 values of the final basis.
+                const bool origin = blk_max<NT>(origin_out ? 1.0 : 0.0, sh) == 0.0;
+                if (st0 == kUnbounded && (primal_ok || origin)) {
                     // Ray of the entering variable q.
+                    if (tid == 0) sh->fail = 0;  // a failed primal check is not the ray's
+                    __syncthreads();
                     int q = a.enter[k];
                     if (sub && q >= n && q < n + ms) {
                         const int fr = full_row(q - n);
@@ -435,8 +519,9 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     }
                 }
             }
-            const bool passed = (st0 == kOptimal) ? (cert & LP_CERT_DUAL_OK_BIT) && (cert & LP_CERT_PRIMAL_OK_BIT)
-                                                  : (cert & LP_CERT_RAY_OK_BIT) != 0;
+            const bool passed = phase1 ? (cert & LP_CERT_INFEASIBLE_OK_BIT) != 0
+                                : (st0 == kOptimal) ? (cert & LP_CERT_DUAL_OK_BIT) && (cert & LP_CERT_PRIMAL_OK_BIT)
+                                                    : (cert & LP_CERT_RAY_OK_BIT) != 0;
             fallback = !passed;
             if (passed && st0 == kOptimal) {
                 // FP64 x and objective (fixed summation order by wavefront 0).
@@ -448,7 +533,7 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off);
                     if (lane == 0) a.obj[k] = z;
                 }
-            } else if (passed) {
+            } else if (passed && st0 == kUnbounded) {
                 for (int j = tid; j < n; j += NT) x[j] = __builtin_nan("");
                 if (tid == 0) a.obj[k] = __builtin_inf();
             }
@@ -547,6 +632,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
         const bool work = st0 == kOptimal || st0 == kUnbounded;
         if (a.viol && lane == 0) a.viol[k] = kBig;  // until the primal check counts them
 
+        bool origin_out = false;  // this lane's rows: is x = 0 outside the feasible set?
         if (work) {
             // Rows: sign normalisation and the tight set; columns: the basic set.
             for (int i = lane; i < m; i += 64) {
@@ -555,6 +641,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 const bool neg = bi < 0.0;
                 if (neg && sen != kEQ) sen = (sen == kLE) ? kGE : kLE;
                 rowf[i] = (neg ? kRowNeg : 0) | (sen << 1) | (sub ? 0 : kTight);
+                origin_out |= sen != kLE && bi != 0.0;
             }
             for (int j = lane; j < n; j += 64) colf[j] = 0;
             wave_sync();
@@ -829,7 +916,10 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                         else if (sen == kGE) df &= yt <= tol_d;
                     }
                     if (wave_all(df)) cert |= LP_CERT_DUAL_OK_BIT;
-                } else if (st0 == kUnbounded && primal_ok) {
+                }
+                // x = 0 feasible: the ray alone proves the LP unbounded.
+                const bool origin = !__ballot(origin_out);
+                if (st0 == kUnbounded && (primal_ok || origin)) {
                     // Ray of the entering variable q: w = B^-1 a_q, d_S = -w.
                     int q = a.enter[k];
                     if (sub && q >= n && q < n + ms) {

@@ -13,7 +13,7 @@ constexpr int kBig = 0x7fffffff;
 constexpr int kRowNeg = 1, kRowDead = 8, kRowPad = 16;
 // Certificate outcome bits (stats[5]); the values of LP_CERT_* in lpbatch.h.
 constexpr int LP_CERT_PRIMAL_OK_BIT = 1, LP_CERT_DUAL_OK_BIT = 2, LP_CERT_RAY_OK_BIT = 4,
-              LP_CERT_SINGULAR_BIT = 8;
+              LP_CERT_SINGULAR_BIT = 8, LP_CERT_INFEASIBLE_OK_BIT = 16;
 
 template <typename T> __device__ __forceinline__ T t_inf();
 template <> __device__ __forceinline__ float t_inf<float>() { return __builtin_inff(); }

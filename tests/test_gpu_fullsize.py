@@ -67,6 +67,19 @@ def test_uneven_full_autotuned(env, precision):
     assert np.all(st[bt.meta["unbounded"]] == oracle.UNBOUNDED)
     # LPs the one-wavefront kernel cannot take ran in the workgroup kernel.
     assert np.sum(stats[:, 6] >= 2) > 5000
+    if precision == 1:
+        # Infeasible results are proven in FP64 from the FP32 Phase I basis
+        # (a Farkas certificate), not re-solved.
+        inf = np.asarray(bt.meta["infeasible"])
+        proven = (stats[inf, 5] & 16) != 0
+        assert np.mean(proven) > 0.9, np.mean(proven)
+        assert np.all(stats[inf][proven, 3] == 0)
+        # The bit is given to infeasible results only.
+        assert np.all(st[(stats[:, 5] & 16) != 0] == oracle.INFEASIBLE)
+        # Unbounded results: the FP64 ray (x = 0 is feasible for these LPs).
+        unb = np.asarray(bt.meta["unbounded"])
+        assert np.mean((stats[unb, 5] & 4) != 0) > 0.99
+        assert np.all(st[(stats[:, 5] & 4) != 0] == oracle.UNBOUNDED)
     # The tuned table, used without the flag: the same results.
     st2, obj2, x2, _ = _solve(env, bt, precision=precision)
     assert_parity(bt, st2, obj2, x2, ref)

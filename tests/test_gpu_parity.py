@@ -217,7 +217,15 @@ def test_fp32_certified_two_phase_and_uneven(ctx):
     bt = W.uneven_batch(200, seed=1002)
     st, obj, x, stats, ref = check_fp32(ctx, bt)
     assert np.any((stats[:, 5] & 4) != 0)   # unbounded rays certified in FP64
-    assert np.any(stats[:, 3] >= 1)          # infeasible LPs went to the FP64 re-solve
+    # Infeasible results proven by the FP64 Phase I certificate, not re-solved.
+    inf = np.asarray(bt.meta["infeasible"])
+    assert np.all((stats[inf, 5] & 16) != 0)
+    assert np.all(stats[inf, 3] == 0)
+    assert np.all(st[(stats[:, 5] & 16) != 0] == oracle.INFEASIBLE)
+    # Rows all <= with b >= 0: x = 0 is feasible, so the FP64 ray alone
+    # certifies an unbounded result.
+    unb = np.asarray(bt.meta["unbounded"])
+    assert np.all((stats[unb, 5] & 4) != 0)
 
 
 def test_fp32_certified_support_and_large(ctx):
