@@ -169,6 +169,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
             const uint64_t tmask = __ballot(lane < m && (rf & kTightD));
             const uint64_t smask = __ballot(isbasic);
             const int kt = __popcll(tmask), K = __popcll(smask);
+            const int KL = K | 1;  // M's column stride: odd, so row reads of M miss no bank twice
             const int tpos = (tmask >> lane) & 1 ? __popcll(tmask & lanemask_lt(lane)) : -1;
             const int spos = isbasic ? __popcll(smask & lanemask_lt(lane)) : -1;
             if (tpos >= 0) tlist[tpos] = lane;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
 #pragma unroll
                     for (int q = 0; q < CG; ++q)
                         if (s0 + q < K && lane < K) {
-                            M[(s0 + q) * K + lane] = vv[q];
+                            M[(s0 + q) * KL + lane] = vv[q];
                             am = fmax(am, fabs(vv[q]));
                         }
                 }
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
                     const bool act = lane < K && pos == kBig;
                     const int la = act ? lane : pl;
                     const double l = colv * uinv;
-                    if (act) M[p * K + lane] = l;
+                    if (act) M[p * KL + lane] = l;
                     double nextv = 0.0;
                     if (act) {
                         for (int j0 = p + 1; j0 < K; j0 += CG) {
@@ -236,13 +237,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
 #pragma unroll
                             for (int q = 0; q < CG; ++q) {
                                 const int j = j0 + q < K ? j0 + q : K - 1;
-                                pr[q] = M[j * K + pl];
-                                mr[q] = M[j * K + la];
+                                pr[q] = M[j * KL + pl];
+                                mr[q] = M[j * KL + la];
                             }
 #pragma unroll
                             for (int q = 0; q < CG; ++q) {
                                 const double u = fma(-l, pr[q], mr[q]);
-                                if (j0 + q < K) M[(j0 + q) * K + lane] = u;
+                                if (j0 + q < K) M[(j0 + q) * KL + lane] = u;
                                 if (q == 0 && j0 == p + 1) nextv = u;
                             }
                         }
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
 #pragma unroll
                         for (int q = 0; q < CG; ++q) {
                             const int p = p0 + q < K ? p0 + q : K - 1;
-                            mv[q] = M[p * K + lane];
-                            mu[q] = M[lane * K + op[q]];
+                            mv[q] = M[p * KL + lane];
+                            mu[q] = M[lane * KL + op[q]];
                         }
                     }
 #pragma unroll
@@ -291,8 +292,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
 #pragma unroll
                         for (int q = 0; q < CG; ++q) {
                             const int p = h - q >= 0 ? h - q : 0;
-                            mv[q] = M[p * K + lane];
-                            ml[q] = M[lane * K + op[q]];
+                            mv[q] = M[p * KL + lane];
+                            ml[q] = M[lane * KL + op[q]];
                         }
                     }
 #pragma unroll
@@ -400,14 +401,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
                         if (lane < K) rw = (q < n) ? sgt * tab[q * ldm + tl] : (lane == tr ? sq : 0.0);
                         for (int p = 0; p < K; ++p) {
                             const double zp = lane_get(rw, order[p]);
-                            if (lane < K && pos > p) rw = fma(-M[p * K + lane], zp, rw);
+                            if (lane < K && pos > p) rw = fma(-M[p * KL + lane], zp, rw);
                         }
                         double wd = 0.0;
                         for (int p = K - 1; p >= 0; --p) {
                             const int pl = order[p];
-                            const double xp = lane_get(rw, pl) / M[p * K + pl];
+                            const double xp = lane_get(rw, pl) / M[p * KL + pl];
                             if (lane == p) wd = xp;
-                            if (lane < K && pos < p) rw = fma(-M[p * K + lane], xp, rw);
+                            if (lane < K && pos < p) rw = fma(-M[p * KL + lane], xp, rw);
                         }
                         const double tol_r = a.tol_feas;
                         bool ok2 = !(lane < K) || -wd >= -tol_r;

@@ -93,7 +93,8 @@ __device__ __forceinline__ void blk_argmax(double &key, int &idx, CertCtrl<NT> *
 }
 
 // Compacts the flagged entries of [0, count) into list (ascending); wave 0 only.
-__device__ __forceinline__ int compact(const int *flag, int mask, int count, int *list, int *pos)
+__device__ __forceinline__ int compact(const int *flag, int mask, int count, int *list, int *pos,
+                                      int cap = 0x7fffffff)
 {
     const int lane = threadIdx.x & 63;
     int base = 0;
@@ -103,7 +104,7 @@ __device__ __forceinline__ int compact(const int *flag, int mask, int count, int
         const uint64_t b = __ballot(on);
         if (on) {
             const int p = base + __popcll(b & lanemask_lt(lane));
-            list[p] = i;
+            if (p < cap) list[p] = i;  // a list holds cap entries; the count goes on
             pos[i] = p;
         } else if (i < count) {
             pos[i] = -1;
@@ -577,11 +578,14 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
     constexpr int CG = W >= 16 ? 4 : 8;
     int64_t off = 0;
     if constexpr (STAGE) {
+        // Rows at an odd stride of doubles: lanes reading one row each (the
+        // LU's gather of B_TS, the primal check) then hit distinct banks.
         double *As = reinterpret_cast<double *>(smem);
+        const int lds_n = a.un | 1;
         const int64_t cnt = int64_t(a.um) * a.un;
-        for (int64_t e = threadIdx.x; e < cnt; e += 64 * W) As[e] = a.A[e];
+        for (int64_t e = threadIdx.x; e < cnt; e += 64 * W) As[(e / a.un) * lds_n + e % a.un] = a.A[e];
         __syncthreads();
-        off = align16(8 * cnt);
+        off = align16(8 * int64_t(a.um) * lds_n);
     }
     char *my = smem + off + int64_t(wave) * a.wave_bytes;
     const int64_t total = a.num;
@@ -600,6 +604,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
         // A stays in one address space per instantiation (LDS when staged),
         // so its loads compile to LDS or global instructions, not flat ones.
         const double *A = STAGE ? reinterpret_cast<const double *>(smem) : a.A + (a.shared ? 0 : ao);
+        const int lda = STAGE ? (n | 1) : n;  // row stride of A
         const double *b = a.b + ro, *c = a.c + co;
         const int8_t *sense = a.sense + ro;
         const int32_t *basis = a.basis + ro;
@@ -681,8 +686,11 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 }
             }
             wave_sync();
-            const int kt = compact(rowf, kTight, m, tlist, tpos);
-            const int K = compact(colf, kTight, n, slist, spos);
+            // (Lists of 64 entries: more tight rows or basic structurals than
+            // that fail the K <= kl test below.)
+            const int kt = compact(rowf, kTight, m, tlist, tpos, 64);
+            const int K = compact(colf, kTight, n, slist, spos, 64);
+            const int KL = K | 1;  // M's column stride: odd, so row reads of M miss no bank twice
             wave_sync();
             double bm = 0.0, cm = 0.0;
             for (int i = lane; i < m; i += 64) bm = fmax(bm, fabs(b[i]));
@@ -696,7 +704,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
             double *M = reinterpret_cast<double *>(my + L.mat);
             // Lane t holds the t-th tight row (index and sign) and lane s the
             // s-th basic structural, so loops over T or S read them with
-            // readlane instead of LDS.  M is B_TS column-major (M[s*K + t],
+            // readlane instead of LDS.  M is B_TS column-major (M[s*KL + t],
             // row t in lane t); every loop over M loads CG entries ahead.
             const bool kfit = K <= a.kl;
             const int tl = (lane < K && kfit) ? tlist[lane] : 0;
@@ -713,7 +721,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                 // update; the pivot comes from its owner's register, so a step
                 // reads only the pivot row and this lane's row segment from LDS.
                 double colv = 0.0;
-                const double *At = A + int64_t(tl) * n;
+                const double *At = A + int64_t(tl) * lda;
                 // (LDS and A reads are issued by the K lanes that own rows only:
                 // their cost scales with the active lanes.)
                 for (int s0 = 0; s0 < K; s0 += CG) {
@@ -729,7 +737,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 #pragma unroll
                     for (int q = 0; q < CG; ++q)
                         if (s0 + q < K && lane < K) {
-                            M[(s0 + q) * K + lane] = v[q];
+                            M[(s0 + q) * KL + lane] = v[q];
                             am = fmax(am, fabs(v[q]));
                         }
                 }
@@ -753,7 +761,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                     const bool act = lane < K && pos == kBig;
                     const int la = act ? lane : pl;
                     const double l = colv * uinv;
-                    if (act) M[p * K + lane] = l;
+                    if (act) M[p * KL + lane] = l;
                     double nextv = 0.0;
                     if (act) {
                         for (int j0 = p + 1; j0 < K; j0 += CG) {
@@ -761,13 +769,13 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 #pragma unroll
                             for (int q = 0; q < CG; ++q) {
                                 const int j = j0 + q < K ? j0 + q : K - 1;
-                                pr[q] = M[j * K + pl];
-                                mr[q] = M[j * K + la];
+                                pr[q] = M[j * KL + pl];
+                                mr[q] = M[j * KL + la];
                             }
 #pragma unroll
                             for (int q = 0; q < CG; ++q) {
                                 const double u = fma(-l, pr[q], mr[q]);
-                                if (j0 + q < K) M[(j0 + q) * K + lane] = u;
+                                if (j0 + q < K) M[(j0 + q) * KL + lane] = u;
                                 if (q == 0 && j0 == p + 1) nextv = u;
                             }
                         }
@@ -792,8 +800,8 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 #pragma unroll
                         for (int q = 0; q < CG; ++q) {
                             const int p = p0 + q < K ? p0 + q : K - 1;
-                            mv[q] = M[p * K + lane];               // lane t: L[t][p] (rows below p)
-                            mu[q] = M[lane * K + op[q]];           // lane j: U[p][j]
+                            mv[q] = M[p * KL + lane];               // lane t: L[t][p] (rows below p)
+                            mu[q] = M[lane * KL + op[q]];           // lane j: U[p][j]
                         }
                     }
 #pragma unroll
@@ -817,8 +825,8 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
 #pragma unroll
                         for (int q = 0; q < CG; ++q) {
                             const int p = h - q >= 0 ? h - q : 0;
-                            mv[q] = M[p * K + lane];               // lane t: U[pos_t][p]
-                            ml[q] = M[lane * K + op[q]];           // lane p': L[p][p']
+                            mv[q] = M[p * KL + lane];               // lane t: U[pos_t][p]
+                            ml[q] = M[lane * KL + op[q]];           // lane p': L[p][p']
                         }
                     }
 #pragma unroll
@@ -848,7 +856,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                     const int i = i0 + lane;
                     const int f = (i < m) ? rowf[i] : kTight;
                     const bool act = !(f & kTight);
-                    const double *Ai = A + int64_t(act ? i : 0) * n;
+                    const double *Ai = A + int64_t(act ? i : 0) * lda;
                     double ax[4] = {0.0, 0.0, 0.0, 0.0};
                     for (int s0 = 0; s0 < K; s0 += CG) {
                         int si[CG];
@@ -902,7 +910,7 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                             if (act) {  // only non-basic columns read A
                                 double av[CG];
 #pragma unroll
-                                for (int q = 0; q < CG; ++q) av[q] = A[int64_t(ti[q]) * n + jc];
+                                for (int q = 0; q < CG; ++q) av[q] = A[int64_t(ti[q]) * lda + jc];
 #pragma unroll
                                 for (int q = 0; q < CG; ++q)
                                     if (t0 + q < K) ya[q & 3] = fma(yq[q], av[q], ya[q & 3]);
@@ -942,18 +950,18 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                         if (lane < K) {
                             const int i = tlist[lane];
                             const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
-                            rw = (q < n) ? sg * A[int64_t(i) * n + q] : (lane == tr ? sq : 0.0);
+                            rw = (q < n) ? sg * A[int64_t(i) * lda + q] : (lane == tr ? sq : 0.0);
                         }
                         for (int p = 0; p < K; ++p) {
                             const double zp = lane_get(rw, order[p]);
-                            if (lane < K && pos > p) rw = fma(-M[p * K + lane], zp, rw);
+                            if (lane < K && pos > p) rw = fma(-M[p * KL + lane], zp, rw);
                         }
                         double wd = 0.0;
                         for (int p = K - 1; p >= 0; --p) {
                             const int pl = order[p];
-                            const double xp = lane_get(rw, pl) / M[p * K + pl];
+                            const double xp = lane_get(rw, pl) / M[p * KL + pl];
                             if (lane == p) wd = xp;
-                            if (lane < K && pos < p) rw = fma(-M[p * K + lane], xp, rw);
+                            if (lane < K && pos < p) rw = fma(-M[p * KL + lane], xp, rw);
                         }
                         const double tol_r = a.tol_feas;
                         bool ok2 = !(lane < K) || -wd >= -tol_r;
@@ -965,8 +973,8 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
                             const int f = rowf[i];
                             if (f & kTight) continue;
                             const double sg = (f & kRowNeg) ? -1.0 : 1.0;
-                            double ad = (q < n) ? A[int64_t(i) * n + q] : 0.0;
-                            for (int s2 = 0; s2 < K; ++s2) ad = fma(A[int64_t(i) * n + slist[s2]], -xsv[s2], ad);
+                            double ad = (q < n) ? A[int64_t(i) * lda + q] : 0.0;
+                            for (int s2 = 0; s2 < K; ++s2) ad = fma(A[int64_t(i) * lda + slist[s2]], -xsv[s2], ad);
                             const double dr = -sg * ad;
                             const int sen = (f >> 1) & 3;
                             if ((f & kDeadRow) || sen == kEQ) ok2 &= fabs(dr) <= tol_r;

@@ -114,9 +114,9 @@ __host__ __device__ inline WaveCertLayout wave_cert_layout(int m, int n, int kl)
     L.tlist = o; o += 256;
     L.slist = o; o += 256;
     L.order = o; o += 256;
-    L.xs = o; o += 512;
-    L.yv = o; o += 512;
-    L.mat = o; o = align16(o + 8 * int64_t(kl) * kl);
+    L.xs = o; o = align16(o + 8 * int64_t(kl));  // x_S and y_T: k <= kl entries
+    L.yv = o; o = align16(o + 8 * int64_t(kl));
+    L.mat = o; o = align16(o + 8 * int64_t(kl) * (kl | 1));  // column stride k | 1
     L.end = o;
     return L;
 }

@@ -868,7 +868,7 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             // more basic structurals, rare at these sizes, goes to the FP64
             // re-solve).  Shared constraints are copied into LDS once per
             // workgroup of W wavefronts when they fit next to W wavefront regions.
-            const int64_t a_bytes = lpb::align16(8 * int64_t(P_full.m0) * P_full.n0);
+            const int64_t a_bytes = lpb::align16(8 * int64_t(P_full.m0) * (P_full.n0 | 1));  // rows at an odd stride
             int W = 1, kl = std::min(kmax, 32), stage = 0;
             int64_t wb = lpb::wave_cert_layout(P_full.m_max, P_full.n_max, kl).end, lds = wb;
             if (shared && a_bytes <= 65536) {
