@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
         int qv = 0;
         if (lane == 0) qv = int(atomicInc(reinterpret_cast<unsigned *>(a.queue), 0xffffffffu));
         const int64_t k = F.k;
-        const int m = F.m, n = F.n, ldm = dense_ldm(m);
+        const int m = uniform(F.m), n = uniform(F.n), ldm = dense_ldm(m);
         const int64_t co = F.co;
         // A scattered from flat row-major order into the columns (element
         // f = lane + 64 t: row f / n, column f % n); entries past m * n read 0.

@@ -688,8 +688,10 @@ __global__ __launch_bounds__(64 * W) void certify_wave_kernel(CertArgs a)
             wave_sync();
             // (Lists of 64 entries: more tight rows or basic structurals than
             // that fail the K <= kl test below.)
-            const int kt = compact(rowf, kTight, m, tlist, tpos, 64);
-            const int K = compact(colf, kTight, n, slist, spos, 64);
+            // (Counts made wavefront-uniform for the compiler: loop bounds and
+            // M's strides then live in scalar registers.)
+            const int kt = uniform(compact(rowf, kTight, m, tlist, tpos, 64));
+            const int K = uniform(compact(colf, kTight, n, slist, spos, 64));
             const int KL = K | 1;  // M's column stride: odd, so row reads of M miss no bank twice
             wave_sync();
             double bm = 0.0, cm = 0.0;
