@@ -157,6 +157,7 @@ struct lp_ctx {
     bool counters_dirty = false;  // a failed call may have left work counters non-zero
     int num_cu = 0;
     int max_lds = 0;
+    int lds_per_cu = 0;  // LDS of one compute unit, shared by its resident workgroups
     lpb::DevBuf scratch, meta, counters;
     lpb::DevBuf scaled, scale_meta;  // lp_options.scaling: scaled copy, shapes
     std::vector<lpb::KernelTime> times;

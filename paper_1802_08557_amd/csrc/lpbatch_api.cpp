@@ -81,6 +81,17 @@ int64_t lds_budget(const lp_ctx *ctx, int placement)
     return placement == LP_PLACE_LDS ? ctx->max_lds : ctx->max_lds / 3;
 }
 
+// LDS for one workgroup of the workgroup kernel that keeps per_cu of them
+// resident: when registers already cap a CU at per_cu workgroups, each may
+// take the CU's LDS / per_cu, and every LP whose tableau fits there next to
+// the index arrays is then solved from LDS instead of a device-memory slot.
+int64_t lds_share(const lp_ctx *ctx, bool fp32, int nt, int64_t lds, int per_cu)
+{
+    const int64_t share = std::min<int64_t>(ctx->max_lds, (int64_t(ctx->lds_per_cu) / per_cu) & ~int64_t(255));
+    if (share <= lds) return lds;
+    return lpb::simplex_blocks_per_cu(fp32, nt, int(share)) == per_cu ? share : lds;
+}
+
 // One persistent launch of the wavefront kernel over ids[0 .. num) (or the
 // device list ids[0 .. *list_count)); LPs it cannot take are appended to
 // defer_ids from defer_base on.
@@ -153,10 +164,11 @@ int queue_pass(lp_ctx *ctx, const Plan &P, lpb::SolveArgs a, const lp_options &o
     if (lds > ctx->max_lds)
         return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index "
                     "arrays (device limit %d)", P.m_max, ncol_worst, (long long)lds, ctx->max_lds);
-    a.lds_bytes = int32_t(lds);
     a.force_hbm = opts.placement == LP_PLACE_HBM;
     const int per_cu = lpb::simplex_blocks_per_cu(fp32, nt, int(lds));
     if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for %d threads, %lld B LDS", nt, (long long)lds);
+    if (!a.force_hbm) lds = lds_share(ctx, fp32, nt, lds, per_cu);
+    a.lds_bytes = int32_t(lds);
     // When the wavefront kernel was offered every LP, this launch only drains
     // the few it deferred: one workgroup per CU is plenty and keeps its end cheap.
     const int64_t slots = n_wave > 0 && n_block == 0 ? ctx->num_cu : int64_t(per_cu) * ctx->num_cu;
@@ -268,10 +280,11 @@ int launch_block(lp_ctx *ctx, bool fp32, lpb::SolveArgs a, const BinLaunch &B, c
     if (lds > ctx->max_lds)
         return fail(LP_ERR_ARG, "LP of %d rows x %d columns needs %lld bytes of LDS for its index arrays "
                     "(device limit %d)", B.m_max, ncol_worst, (long long)lds, ctx->max_lds);
-    a.lds_bytes = int32_t(lds);
     a.force_hbm = B.force_hbm;
     const int per_cu = lpb::simplex_blocks_per_cu(fp32, B.nt, int(lds));
     if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for %d threads, %lld B LDS", B.nt, (long long)lds);
+    if (!a.force_hbm) lds = lds_share(ctx, fp32, B.nt, lds, per_cu);
+    a.lds_bytes = int32_t(lds);
     int64_t grid = std::min<int64_t>(num, int64_t(per_cu) * ctx->num_cu);
     if (grid_cap > 0) grid = std::min(grid, grid_cap);
     if (grid < 1) return LP_OK;
@@ -514,6 +527,10 @@ int lp_ctx_create(lp_ctx **out, int device)
     ctx->device = device;
     hipError_t e1 = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     hipError_t e2 = hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (hipDeviceGetAttribute(&ctx->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
+            hipSuccess ||
+        ctx->lds_per_cu < ctx->max_lds)
+        ctx->lds_per_cu = ctx->max_lds;
     if (e1 != hipSuccess || e2 != hipSuccess) {
         delete ctx;
         return fail(LP_ERR_HIP, "lp_ctx_create: device attribute query failed");
