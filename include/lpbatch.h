@@ -64,8 +64,11 @@ typedef enum {
 /* Arithmetic of the tableau.  LP_PREC_FP64: every pivot in double precision.
  * LP_PREC_FP32_CERT64: pivots on a single-precision tableau, then the final
  * basis is re-solved in double precision on the GPU (x_B = B^-1 b, duals,
- * reduced costs); a basis that fails that certificate is re-solved from
- * scratch in double precision, so reported results carry FP64 accuracy. */
+ * reduced costs; the ray of an unbounded result; the Phase I duals of an
+ * infeasible one, see LP_CERT_*); a result that fails that certificate is
+ * refined in double precision from its final basis, or re-solved from the
+ * slack basis when that is not possible, so reported results carry FP64
+ * accuracy. */
 typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32_CERT64 = 1 } lp_precision;
 
 #define LP_OK 0
@@ -79,17 +82,21 @@ typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32_CERT64 = 1 } lp_precision;
 #define LP_STAT_PIVOTS_PHASE1 0 /* Phase I pivots                                    */
 #define LP_STAT_PIVOTS_PHASE2 1 /* Phase II pivots                                   */
 #define LP_STAT_DEGENERATE 2    /* pivots with a zero step                           */
-#define LP_STAT_FALLBACK 3      /* 1: the FP64 re-solve ran from the slack basis;    
-                                   2: it ran from the screened relaxation's basis  */
+#define LP_STAT_FALLBACK 3      /* 1: the FP64 re-solve ran from the slack basis;
+                                   2: it started from the single-precision (or the
+                                   screened relaxation's) final basis              */
 #define LP_STAT_REFINE 4        /* FP64 pivots of the fallback solve                 */
 #define LP_STAT_CERT 5          /* certificate outcome, LP_CERT_* bits              */
 #define LP_STAT_PLACEMENT 6     /* where the tableau lived, LP_PLACE_*              */
 #define LP_STAT_BASIC_STRUCT 7  /* basic structural variables at the end            */
 
-#define LP_CERT_PRIMAL_OK 1
-#define LP_CERT_DUAL_OK 2
+#define LP_CERT_PRIMAL_OK 1 /* x_B = B^-1 b and every row's slack within tolerance   */
+#define LP_CERT_DUAL_OK 2   /* every reduced cost and dual sign within tolerance     */
+/* An unbounded result: the FP64 ray of the entering column keeps every basic
+ * variable and row feasible and raises the objective, and the LP has a
+ * feasible point (the basis passes the primal check, or x = 0 is feasible). */
 #define LP_CERT_RAY_OK 4
-#define LP_CERT_SINGULAR 8
+#define LP_CERT_SINGULAR 8  /* the basis block could not be factorised          */
 /* An infeasible result proven in FP64 from the FP32 solve's final Phase I
  * basis (Phase I optimum below zero, every structural and slack reduced cost
  * within tolerance: -y is a Farkas certificate).  Given by the workgroup
