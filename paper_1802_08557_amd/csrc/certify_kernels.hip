@@ -302,10 +302,25 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     const double inv = 1.0 / M[p * K + p];
                     for (int i = p + 1 + tid; i < K; i += NT) M[i * K + p] *= inv;
                     __syncthreads();
+                    // Trailing update: thread (r0, c0) takes column p+1+c0 of
+                    // rows p+1+r0, p+1+r0+rpp, ... (one division per step, not
+                    // per entry; consecutive threads on consecutive columns).
                     const int rem = K - p - 1;
-                    for (int e = tid; e < rem * rem; e += NT) {
-                        const int i = p + 1 + e / rem, j = p + 1 + e % rem;
-                        M[i * K + j] = fma(-M[i * K + p], M[p * K + j], M[i * K + j]);
+                    if (rem == 0) {
+                        // last step: nothing below the pivot
+                    } else if (rem <= NT) {
+                        const int rpp = NT / rem;
+                        if (tid < rpp * rem) {
+                            const int r0 = tid / rem, j = p + 1 + (tid - r0 * rem);
+                            const double upj = M[p * K + j];
+                            for (int i = p + 1 + r0; i < K; i += rpp)
+                                M[i * K + j] = fma(-M[i * K + p], upj, M[i * K + j]);
+                        }
+                    } else {
+                        for (int j = p + 1 + tid; j < K; j += NT) {
+                            const double upj = M[p * K + j];
+                            for (int i = p + 1; i < K; ++i) M[i * K + j] = fma(-M[i * K + p], upj, M[i * K + j]);
+                        }
                     }
                     __syncthreads();
                 }
