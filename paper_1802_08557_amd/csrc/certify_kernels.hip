@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
     int64_t item = blockIdx.x;
     while (item < total) {
         if (tid == 0) sh->next = int(gridDim.x) + atomicAdd(a.queue, 1);
-        const int64_t k = item;
+        const int64_t k = !a.order1 ? item : (item < a.n1 ? a.order1[item] : a.order2[item - a.n1]);
         int m, n;
         int64_t ao, ro, co;
         if (a.um > 0) {
@@ -249,12 +249,24 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                 M = (mat_off + 8 * int64_t(K) * K <= a.lds_bytes)
                         ? reinterpret_cast<double *>(smem + mat_off)
                         : reinterpret_cast<double *>(a.scratch + int64_t(blockIdx.x) * a.slot_bytes);
-                // B_TS, row-major K x K, sign-normalised.
-                for (int e = tid; e < K * K; e += NT) {
-                    const int t = e / K, s2 = e - t * K;
-                    const int i = tlist[t];
-                    const double sg = (rowf[i] & kRowNeg) ? -1.0 : 1.0;
-                    M[e] = sg * A[int64_t(i) * n + slist[s2]];
+                // B_TS, row-major K x K, sign-normalised: thread columns s2,
+                // rows in groups of 8 whose loads precede their stores.
+                for (int s2 = tid; s2 < K; s2 += NT) {
+                    const int jc = slist[s2];
+                    for (int t0 = 0; t0 < K; t0 += 8) {
+                        double v[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int t = t0 + q;
+                            if (t < K) {
+                                const int i = tlist[t];
+                                v[q] = ((rowf[i] & kRowNeg) ? -1.0 : 1.0) * A[int64_t(i) * n + jc];
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (t0 + q < K) M[(t0 + q) * K + s2] = v[q];
+                    }
                 }
                 for (int t = tid; t < K; t += NT) {
                     const int i = tlist[t];
@@ -305,22 +317,40 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                     // Trailing update: thread (r0, c0) takes column p+1+c0 of
                     // rows p+1+r0, p+1+r0+rpp, ... (one division per step, not
                     // per entry; consecutive threads on consecutive columns).
+                    // Rows go in groups of LB whose loads are all issued before
+                    // any store, so a block in device memory costs one round
+                    // trip per group rather than one per row.
                     const int rem = K - p - 1;
+                    constexpr int LB = 8;
+                    auto update_column = [&](int j, int i_first, int di) {
+                        const double upj = M[p * K + j];
+                        for (int i0 = i_first; i0 < K; i0 += LB * di) {
+                            double lv[LB], mv[LB];
+#pragma unroll
+                            for (int q = 0; q < LB; ++q) {
+                                const int i = i0 + q * di;
+                                if (i < K) {
+                                    lv[q] = M[i * K + p];
+                                    mv[q] = M[i * K + j];
+                                }
+                            }
+#pragma unroll
+                            for (int q = 0; q < LB; ++q) {
+                                const int i = i0 + q * di;
+                                if (i < K) M[i * K + j] = fma(-lv[q], upj, mv[q]);
+                            }
+                        }
+                    };
                     if (rem == 0) {
                         // last step: nothing below the pivot
                     } else if (rem <= NT) {
                         const int rpp = NT / rem;
                         if (tid < rpp * rem) {
-                            const int r0 = tid / rem, j = p + 1 + (tid - r0 * rem);
-                            const double upj = M[p * K + j];
-                            for (int i = p + 1 + r0; i < K; i += rpp)
-                                M[i * K + j] = fma(-M[i * K + p], upj, M[i * K + j]);
+                            const int r0 = tid / rem;
+                            update_column(p + 1 + (tid - r0 * rem), p + 1 + r0, rpp);
                         }
                     } else {
-                        for (int j = p + 1 + tid; j < K; j += NT) {
-                            const double upj = M[p * K + j];
-                            for (int i = p + 1; i < K; ++i) M[i * K + j] = fma(-M[i * K + p], upj, M[i * K + j]);
-                        }
+                        for (int j = p + 1 + tid; j < K; j += NT) update_column(j, p + 1, 1);
                     }
                     __syncthreads();
                 }

@@ -89,6 +89,11 @@ struct CertArgs {
     char *scratch;            // LU matrices too large for LDS, one slot per workgroup
     int64_t slot_bytes;
     int32_t *queue, *done;
+    // Workgroup kernel, optional: work item t is LP order1[t] for t < n1, else
+    // order2[t - n1] (largest LPs first, so the launch does not end on one);
+    // NULL: item t is LP t.
+    const int32_t *order1, *order2;
+    int64_t n1;
     int32_t lds_bytes;
     double tol_feas, tol_opt; // certificate tolerances (relative, as in SolveParams)
     // Wavefront kernels only: LDS bytes per wavefront (the dense kernel: the

@@ -924,6 +924,12 @@ int lp_batch_solve_ex(lp_ctx *ctx, int64_t num_lps, const double *A, const doubl
             if (per_cu < 1) return fail(LP_ERR_HIP, "occupancy query failed for the certificate kernel");
             const int64_t cgrid = std::min<int64_t>(num_lps, int64_t(per_cu) * ctx->num_cu);
             ca.slot_bytes = lpb::align16(8 * int64_t(kmax) * kmax);
+            if (!P.uniform && n_block + n_wave == num_lps) {
+                // The workgroup kernel's LPs in its order (largest first), then the rest.
+                ca.order1 = d_defer_ids;
+                ca.n1 = n_block;
+                ca.order2 = d_wave_ids;
+            }
             int rc2 = ctx->scratch.ensure(std::max<size_t>(ctx->scratch.bytes, size_t(ca.slot_bytes) * size_t(cgrid)));
             if (rc2 != LP_OK) return rc2;
             ca.scratch = static_cast<char *>(ctx->scratch.p);
