@@ -79,6 +79,12 @@ __device__ __forceinline__ void wave_argmin(T &k1, int &k2, int &p)
     }
 }
 
+// The same lexicographic argmin with DPP / permlane reductions instead of
+// shuffles through LDS: the least k1, then the least k2 among the lanes that
+// hold it, then p from the lowest lane holding both (all 64 lanes active).
+template <typename T>
+__device__ __forceinline__ void wave_argmin_dpp(T &k1, int &k2, int &p);
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
@@ -185,6 +191,19 @@ __device__ __forceinline__ T wave_max_f(T v)
     v = fmax(a, b);
     swap32_f(v, a, b);
     return fmax(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_argmin_dpp(T &k1, int &k2, int &p)
+{
+    const T best = wave_min_f(k1);
+    const bool tie = k1 == best;
+    const int kmin = wave_min_i(tie ? k2 : kBig);
+    const uint64_t win = __ballot(tie && k2 == kmin);
+    const int src = win ? __builtin_ctzll(win) : 0;
+    k1 = best;
+    k2 = kmin;
+    p = lane_get(p, src);
 }
 
 // Called once per workgroup (one thread) when it leaves its work loop: the

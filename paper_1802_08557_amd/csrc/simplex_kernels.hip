@@ -67,7 +67,7 @@ __device__ __forceinline__ int row_sense(int f) { return (f >> 1) & 3; }
 template <typename T, int NT>
 __device__ __forceinline__ void block_argmin(T &k1, int &k2, int &p, Ctrl<T> *sh)
 {
-    wave_argmin(k1, k2, p);
+    wave_argmin_dpp(k1, k2, p);
     if constexpr (NT > 64) {
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) { sh->rv[w] = k1; sh->ri[w] = k2; sh->rp[w] = p; }
