@@ -316,8 +316,8 @@ int autotune_bin(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, BinLaunch B, i
 {
     hipEvent_t e0 = lpb::take_event(ctx), e1 = lpb::take_event(ctx);
     if (!e0 || !e1) return fail(LP_ERR_HIP, "could not create timing events");
-    float best = 1e30f;
-    lpb::TuneEntry choice{default_threads(bin), 0};
+    float best = 1e30f, best_place[2] = {1e30f, 1e30f};
+    lpb::TuneEntry choice{default_threads(bin), 0}, choice_place[2] = {choice, choice};
     const int cand_nt[4] = {64, 128, 256, 512};
     // One untimed launch first (cold caches would otherwise count against the
     // first candidate), then every candidate twice, its faster time kept.
@@ -337,8 +337,14 @@ int autotune_bin(lp_ctx *ctx, bool fp32, const lpb::SolveArgs &a, BinLaunch B, i
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (rep >= 0 && ms < best) { best = ms; choice = lpb::TuneEntry{nt, hbm}; }
+                if (rep >= 0 && ms < best_place[hbm]) { best_place[hbm] = ms; choice_place[hbm] = lpb::TuneEntry{nt, hbm}; }
             }
+    // Device-memory placement only when it wins by 5 %: the sample holds at
+    // most 512 LPs, and on whole mixed batches the LDS share measured faster
+    // whenever the two were within a few percent on the sample.
+    const int pick = best_place[1] < 0.95f * best_place[0] ? 1 : 0;
+    best = best_place[pick];
+    choice = choice_place[pick];
     ctx->tune[lpb::tune_key(bin, fp32)] = choice;
     ctx->events_used -= 2;  // give the two events back to the pool
     return LP_OK;
