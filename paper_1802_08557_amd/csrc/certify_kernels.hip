@@ -54,7 +54,7 @@ struct CertCtrl {
 template <int NT>
 __device__ __forceinline__ double blk_max(double v, CertCtrl<NT> *sh)
 {
-    v = wave_max(v);
+    v = wave_max_f(v);
     if constexpr (NT > 64) {
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) sh->rd[w] = v;
@@ -71,11 +71,12 @@ __device__ __forceinline__ double blk_max(double v, CertCtrl<NT> *sh)
 template <int NT>
 __device__ __forceinline__ void blk_argmax(double &key, int &idx, CertCtrl<NT> *sh)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ok = __shfl_xor(key, off);
-        const int oi = __shfl_xor(idx, off);
-        if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+    {
+        // Within the wavefront: DPP / permlane reductions and a ballot.
+        const double best = wave_max_f(key);
+        const int imin = wave_min_i(key == best ? idx : kBig);
+        key = best;
+        idx = imin;
     }
     if constexpr (NT > 64) {
         const int w = threadIdx.x >> 6;
