@@ -131,7 +131,7 @@ struct LP {
 // pivot row prow_j = t_lj / PE (1 / PE in column e) and the pivot column
 // pcol_i = t_ie (0 for dropped rows; row m is the objective row).  No barrier.
 template <typename T, int NT>
-__device__ __forceinline__ void pivot_vectors(LP<T, NT> &P, int l, int e)
+__device__ __forceinline__ void pivot_vectors(LP<T, NT> &P, int l, int e, bool have_col = false)
 {
     const int tid = threadIdx.x;
     const T *tab = P.tab;
@@ -139,8 +139,14 @@ __device__ __forceinline__ void pivot_vectors(LP<T, NT> &P, int l, int e)
     const T pe = tab[(int64_t)l * ld + e];
     for (int j = tid; j < C; j += NT)
         P.prow[j] = (j == e) ? T(1) / pe : tab[(int64_t)l * ld + j] / pe;
-    for (int i = tid; i <= m; i += NT)
-        P.pcol[i] = (i < m && (P.rowf[i] & ROW_DEAD)) ? T(0) : tab[(int64_t)i * ld + e];
+    // have_col: Step 2 already stored rows 0..m-1 of the column (same thread
+    // per row), so only the objective row's entry is read here.
+    if (have_col) {
+        if (tid == 0) P.pcol[m] = tab[(int64_t)m * ld + e];
+    } else {
+        for (int i = tid; i <= m; i += NT)
+            P.pcol[i] = (i < m && (P.rowf[i] & ROW_DEAD)) ? T(0) : tab[(int64_t)i * ld + e];
+    }
 }
 
 // Step 3's sweep: every tableau entry t_ij becomes fma(-pcol_i, prow_j, t_ij)
@@ -343,9 +349,14 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
         const int e = p;
         // Step 2: leaving row.
         k1 = t_inf<T>(); k2 = BIG; p = -1;
+        const bool keep_col = prm.pricing != 1 && P.iters + 1 < P.cap;  // the look-ahead path reuses it
         for (int i = tid; i < m; i += NT) {
-            if (P.rowf[i] & ROW_DEAD) continue;
+            if (P.rowf[i] & ROW_DEAD) {
+                if (keep_col) P.pcol[i] = T(0);
+                continue;
+            }
             const T a = tab[(int64_t)i * ld + e];
+            if (keep_col) P.pcol[i] = a;
             if (a > tol_piv) {
                 const T bi = tab[(int64_t)i * ld + N];
                 const T th = (bi > T(0) ? bi : T(0)) / a;
@@ -368,7 +379,7 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
         // objective row, one column and the right-hand sides of it, computed
         // here from the pivot's vectors without sweeping the tableau.  When
         // they find a second pivot both go through one sweep (sweep2).
-        pivot_vectors<T, NT>(P, l, e);
+        pivot_vectors<T, NT>(P, l, e, true);
         if (tid == 0) {
             const int t = P.basis[l];
             P.basis[l] = P.nonb[e];
@@ -396,8 +407,12 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
             k1 = t_inf<T>(); k2 = BIG; p = -1;
             const T pc2 = P.prow[e2], prhs = P.prow[N];
             for (int i = tid; i < m; i += NT) {
-                if (P.rowf[i] & ROW_DEAD) continue;
+                if (P.rowf[i] & ROW_DEAD) {
+                    P.pcol2[i] = T(0);
+                    continue;
+                }
                 const T a = (i == l) ? pc2 : fma(-P.pcol[i], pc2, tab[(int64_t)i * ld + e2]);
+                P.pcol2[i] = a;  // the second pivot's column, if this step finds a row
                 if (a > tol_piv) {
                     const T bi = (i == l) ? prhs : fma(-P.pcol[i], prhs, tab[(int64_t)i * ld + N]);
                     const T th = (bi > T(0) ? bi : T(0)) / a;
@@ -428,11 +443,10 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
                                       : fma(-f2, P.prow[j], (j == e) ? T(0) : tab[(int64_t)l2 * ld + j]);
                 P.prow2[j] = (j == e2) ? T(1) / pe2 : t / pe2;
             }
-            for (int i = tid; i <= m; i += NT) {
-                T t = T(0);
-                if (!(i < m && (P.rowf[i] & ROW_DEAD)))
-                    t = (i == l) ? pc2 : fma(-P.pcol[i], pc2, tab[(int64_t)i * ld + e2]);
-                P.pcol2[i] = t;
+            // Rows 0..m-1 of the column were stored by Step 2 above.
+            if (tid == 0) {
+                const int i = m;
+                P.pcol2[i] = fma(-P.pcol[i], pc2, tab[(int64_t)i * ld + e2]);
             }
         }
         __syncthreads();
