@@ -290,12 +290,19 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                 for (int e = tid; e < K * K; e += NT) am = fmax(am, fabs(M[e]));
                 __syncthreads();
                 const double amax = blk_max<NT>(am, sh);
-                // LU with partial pivoting (ties to the smaller row).
+                // LU with partial pivoting (ties to the smaller row).  Column p
+                // of each step is copied into LDS (colb) by the pivot search,
+                // scaled there into the multipliers and read back by the
+                // trailing update, so a block in device memory is read for its
+                // entries and its swapped rows only.
+                double *colb = wv;  // [kmax], free until the ray check
                 for (int p = 0; p < K; ++p) {
                     double key = -1.0;
                     int idx = kBig;
                     for (int i = p + tid; i < K; i += NT) {
-                        const double v = fabs(M[i * K + p]);
+                        const double cv = M[i * K + p];
+                        colb[i] = cv;
+                        const double v = fabs(cv);
                         if (v > key || (v == key && i < idx)) { key = v; idx = i; }
                     }
                     blk_argmax<NT>(key, idx, sh);
@@ -309,36 +316,39 @@ __global__ __launch_bounds__(NT) void certify_kernel(CertArgs a)
                         if (tid == 0) {
                             const double t1 = xs[p]; xs[p] = xs[idx]; xs[idx] = t1;
                             const int t2 = perm[p]; perm[p] = perm[idx]; perm[idx] = t2;
+                            const double t3 = colb[p]; colb[p] = colb[idx]; colb[idx] = t3;
                         }
                     }
                     __syncthreads();
-                    const double inv = 1.0 / M[p * K + p];
-                    for (int i = p + 1 + tid; i < K; i += NT) M[i * K + p] *= inv;
+                    const double inv = 1.0 / colb[p];
+                    for (int i = p + 1 + tid; i < K; i += NT) {
+                        const double l = colb[i] * inv;
+                        M[i * K + p] = l;
+                        colb[i] = l;
+                    }
                     __syncthreads();
                     // Trailing update: thread (r0, c0) takes column p+1+c0 of
                     // rows p+1+r0, p+1+r0+rpp, ... (one division per step, not
                     // per entry; consecutive threads on consecutive columns).
                     // Rows go in groups of LB whose loads are all issued before
-                    // any store, so a block in device memory costs one round
+                    // any store (the compiler may not move a load past a possibly
+                    // aliasing store), so a block in device memory costs one round
                     // trip per group rather than one per row.
                     const int rem = K - p - 1;
-                    constexpr int LB = 8;
+                    constexpr int LB = 16;
                     auto update_column = [&](int j, int i_first, int di) {
                         const double upj = M[p * K + j];
                         for (int i0 = i_first; i0 < K; i0 += LB * di) {
-                            double lv[LB], mv[LB];
+                            double mv[LB];
 #pragma unroll
                             for (int q = 0; q < LB; ++q) {
                                 const int i = i0 + q * di;
-                                if (i < K) {
-                                    lv[q] = M[i * K + p];
-                                    mv[q] = M[i * K + j];
-                                }
+                                if (i < K) mv[q] = M[i * K + j];
                             }
 #pragma unroll
                             for (int q = 0; q < LB; ++q) {
                                 const int i = i0 + q * di;
-                                if (i < K) M[i * K + j] = fma(-lv[q], upj, mv[q]);
+                                if (i < K) M[i * K + j] = fma(-colb[i], upj, mv[q]);
                             }
                         }
                     };
