@@ -27,10 +27,12 @@
 //     <= tol (artificials are not priced again once they left); and the Phase
 //     I optimum w* = -(sum of the artificial values) below -tol.  -y is then
 //     a Farkas certificate of infeasibility.
-// An LP whose result passes is written with its FP64 x and objective; any
-// other LP (failed certificate, singular block, or a status other than
-// optimal / unbounded / invalid input) is appended to the fallback list and
-// re-solved from scratch on the FP64 tableau.
+// An LP whose result passes is written with its FP64 x and objective (an
+// unbounded one with x = NaN and +inf; an infeasible one keeps the solve's
+// NaN outputs); any other
+// LP (failed certificate, singular block, or a status the kernel does not
+// certify) is appended to the fallback list for the FP64 re-solve, which
+// starts from the single-precision final basis where it can.
 #include <math.h>
 
 #include "device_common.h"
