@@ -237,7 +237,7 @@ hipError_t simplex_wave_configure(int max_lds);
 // an LDS-resident tableau would start.  Host and device compute the same layout.
 
 struct LdsLayout {
-    int64_t ctrl, basis, nonb, rowf, colrow, pcol, prow, pcol2, prow2, tab, end_aux;
+    int64_t ctrl, basis, nonb, rowf, colrow, pcol, prow, pcol2, prow2, pcol3, prow3, tab, end_aux;
 };
 
 // ctrl_bytes: size of the control block (type dependent, passed by the caller).
@@ -253,7 +253,9 @@ __host__ __device__ inline LdsLayout lds_layout(int m, int ncol_max, int64_t tsi
     L.prow = align16(L.pcol + tsize * (int64_t)(m + 1));
     L.pcol2 = align16(L.prow + tsize * (int64_t)(ncol_max + 1));
     L.prow2 = align16(L.pcol2 + tsize * (int64_t)(m + 1));
-    L.tab = align16(L.prow2 + tsize * (int64_t)(ncol_max + 1));
+    L.pcol3 = align16(L.prow2 + tsize * (int64_t)(ncol_max + 1));
+    L.prow3 = align16(L.pcol3 + tsize * (int64_t)(m + 1));
+    L.tab = align16(L.prow3 + tsize * (int64_t)(ncol_max + 1));
     L.end_aux = L.tab;
     return L;
 }

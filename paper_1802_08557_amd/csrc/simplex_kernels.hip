@@ -122,6 +122,7 @@ struct LP {
     int *basis, *nonb, *rowf, *colrow;
     T *pcol, *prow;    // pivot column and (scaled) pivot row of a pivot
     T *pcol2, *prow2;  // the same for the second pivot of a fused pair
+    T *pcol3, *prow3;  // and for the third of a fused triple
     T *tab;  // LDS or HBM
     // counters (uniform across the workgroup)
     int iters, it1, degp, cap;
@@ -165,8 +166,8 @@ __device__ __forceinline__ void pivot_vectors(LP<T, NT> &P, int l, int e, bool h
 //     and many accesses in flight -- with a tableau in device memory the
 //     sweep is bound by the accesses in flight, not by the bytes.
 // No barrier.
-template <typename T, int NT, bool PAIR>
-__device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2, int e2)
+template <typename T, int NT, int NP>
+__device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2, int e2, int l3, int e3)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int W = NT / 64;
@@ -178,10 +179,13 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
     const int nv = (C + R - 1) / R;
     const V *pr1 = reinterpret_cast<const V *>(P.prow);
     const V *pr2 = reinterpret_cast<const V *>(P.prow2);
-    // One entry's update: the first pivot's rule, then (PAIR) the second's.
-    auto upd = [&](int i, int j, T v, T w1, T f1, T w2, T f2) {
+    const V *pr3 = reinterpret_cast<const V *>(P.prow3);
+    // One entry's update: the first pivot's rule, then the second's and the
+    // third's (NP pivots).
+    auto upd = [&](int i, int j, T v, T w1, T f1, T w2, T f2, T w3, T f3) {
         T t = (i == l1) ? w1 : fma(-f1, w1, (j == e1) ? T(0) : v);
-        if constexpr (PAIR) t = (i == l2) ? w2 : fma(-f2, w2, (j == e2) ? T(0) : t);
+        if constexpr (NP >= 2) t = (i == l2) ? w2 : fma(-f2, w2, (j == e2) ? T(0) : t);
+        if constexpr (NP >= 3) t = (i == l3) ? w3 : fma(-f3, w3, (j == e3) ? T(0) : t);
         return t;
     };
     const int rw = (64 * U) / nv;  // rows per wavefront step on the narrow path
@@ -189,16 +193,18 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
         for (int i = wave; i <= m; i += W) {
             V *row = reinterpret_cast<V *>(tab + (int64_t)i * ld);
             const T f1 = P.pcol[i];
-            const T f2 = PAIR ? P.pcol2[i] : T(0);
+            const T f2 = NP >= 2 ? P.pcol2[i] : T(0);
+            const T f3 = NP >= 3 ? P.pcol3[i] : T(0);
             for (int k0 = lane; k0 < nv; k0 += 64 * U) {
-                V v[U], w1[U], w2[U];
+                V v[U], w1[U], w2[U], w3[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int k = k0 + 64 * u;
                     if (k < nv) {
                         v[u] = row[k];
                         w1[u] = pr1[k];
-                        if constexpr (PAIR) w2[u] = pr2[k];
+                        if constexpr (NP >= 2) w2[u] = pr2[k];
+                        if constexpr (NP >= 3) w3[u] = pr3[k];
                     }
                 }
 #pragma unroll
@@ -206,7 +212,8 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
                     const int k = k0 + 64 * u;
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        v[u][r] = upd(i, k * R + r, v[u][r], w1[u][r], f1, PAIR ? w2[u][r] : T(0), f2);
+                        v[u][r] = upd(i, k * R + r, v[u][r], w1[u][r], f1, NP >= 2 ? w2[u][r] : T(0), f2,
+                                      NP >= 3 ? w3[u][r] : T(0), f3);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -227,8 +234,8 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
         if (ro[u] >= rw) ro[u] = m + 1;  // past the last row: no item
     }
     for (int i0 = wave * rw; i0 <= m; i0 += W * rw) {
-        V v[U], w1[U], w2[U];
-        T f1[U], f2[U];
+        V v[U], w1[U], w2[U], w3[U];
+        T f1[U], f2[U], f3[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + ro[u];
@@ -236,9 +243,13 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
                 v[u] = reinterpret_cast<const V *>(tab + (int64_t)i * ld)[kv[u]];
                 w1[u] = pr1[kv[u]];
                 f1[u] = P.pcol[i];
-                if constexpr (PAIR) {
+                if constexpr (NP >= 2) {
                     w2[u] = pr2[kv[u]];
                     f2[u] = P.pcol2[i];
+                }
+                if constexpr (NP >= 3) {
+                    w3[u] = pr3[kv[u]];
+                    f3[u] = P.pcol3[i];
                 }
             }
         }
@@ -247,8 +258,8 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
             const int i = i0 + ro[u];
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                v[u][r] = upd(i, kv[u] * R + r, v[u][r], w1[u][r], f1[u], PAIR ? w2[u][r] : T(0),
-                              PAIR ? f2[u] : T(0));
+                v[u][r] = upd(i, kv[u] * R + r, v[u][r], w1[u][r], f1[u], NP >= 2 ? w2[u][r] : T(0),
+                              NP >= 2 ? f2[u] : T(0), NP >= 3 ? w3[u][r] : T(0), NP >= 3 ? f3[u] : T(0));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -261,7 +272,7 @@ __device__ __forceinline__ void sweep_impl(LP<T, NT> &P, int l1, int e1, int l2,
 template <typename T, int NT>
 __device__ __forceinline__ void sweep1(LP<T, NT> &P, int l, int e)
 {
-    sweep_impl<T, NT, false>(P, l, e, -1, -1);
+    sweep_impl<T, NT, 1>(P, l, e, -1, -1, -1, -1);
 }
 
 // Step 3: pivot on (l, e).  Every thread takes part; ends with a barrier.
@@ -290,7 +301,15 @@ __device__ __forceinline__ void pivot(LP<T, NT> &P, int l, int e)
 template <typename T, int NT>
 __device__ __forceinline__ void sweep2(LP<T, NT> &P, int l1, int e1, int l2, int e2)
 {
-    sweep_impl<T, NT, true>(P, l1, e1, l2, e2);
+    sweep_impl<T, NT, 2>(P, l1, e1, l2, e2, -1, -1);
+}
+
+// Three consecutive pivots in one pass (vectors in P.prow3 / P.pcol3 for the
+// third), the same operations in the same order as three sweeps.  No barrier.
+template <typename T, int NT>
+__device__ __forceinline__ void sweep3(LP<T, NT> &P, int l1, int e1, int l2, int e2, int l3, int e3)
+{
+    sweep_impl<T, NT, 3>(P, l1, e1, l2, e2, l3, e3);
 }
 
 // Steps 1-3 until a halt condition.  Returns ST_OPTIMAL, ST_UNBOUNDED or ST_ITER;
@@ -447,17 +466,84 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
             if (tid == 0) {
                 const int i = m;
                 P.pcol2[i] = fma(-P.pcol[i], pc2, tab[(int64_t)i * ld + e2]);
+                const int t = P.basis[l2];
+                P.basis[l2] = P.nonb[e2];
+                P.nonb[e2] = t;
             }
         }
         __syncthreads();
-        sweep2<T, NT>(P, l, e, l2, e2);
-        if (tid == 0) {
-            const int t = P.basis[l2];
-            P.basis[l2] = P.nonb[e2];
-            P.nonb[e2] = t;
+        // Look a third pivot ahead the same way, from both pivots' vectors:
+        // entry (i, j) after the two pivots is
+        //   t'_ij  = (i == l ) ? prow_j  : fma(-pcol_i,  prow_j,  j == e  ? 0 : t_ij)
+        //   t''_ij = (i == l2) ? prow2_j : fma(-pcol2_i, prow2_j, j == e2 ? 0 : t'_ij).
+        int e3 = -1, l3 = -1;
+        if (P.iters + 2 < P.cap) {
+            const bool bland3 = prm.k_deg > 0 && deg_run >= prm.k_deg;
+            const T fm2 = P.pcol2[m];
+            k1 = t_inf<T>(); k2 = BIG; p = -1;
+            for (int j = tid; j < N; j += NT) {
+                const T d1 = fma(-fm, P.prow[j], (j == e) ? T(0) : obj[j]);
+                const T d = fma(-fm2, P.prow2[j], (j == e2) ? T(0) : d1);
+                const int bj = P.nonb[j];
+                if (d > eps_opt && bj < nm) {
+                    const T key = bland3 ? T(0) : -d;
+                    if (key < k1 || (key == k1 && bj < k2)) { k1 = key; k2 = bj; p = j; }
+                }
+            }
+            block_argmin<T, NT>(k1, k2, p, P.sh);
+            e3 = p;
+            if (e3 >= 0) {
+                k1 = t_inf<T>(); k2 = BIG; p = -1;
+                const T pc1 = P.prow[e3], pc2b = P.prow2[e3], prhs1 = P.prow[N], prhs2 = P.prow2[N];
+                for (int i = tid; i < m; i += NT) {
+                    if (P.rowf[i] & ROW_DEAD) {
+                        P.pcol3[i] = T(0);
+                        continue;
+                    }
+                    const T a1 = (i == l) ? pc1 : fma(-P.pcol[i], pc1, (e3 == e) ? T(0) : tab[(int64_t)i * ld + e3]);
+                    const T a = (i == l2) ? pc2b : fma(-P.pcol2[i], pc2b, (e3 == e2) ? T(0) : a1);
+                    P.pcol3[i] = a;
+                    if (a > tol_piv) {
+                        const T b1 = (i == l) ? prhs1 : fma(-P.pcol[i], prhs1, tab[(int64_t)i * ld + N]);
+                        const T bi = (i == l2) ? prhs2 : fma(-P.pcol2[i], prhs2, b1);
+                        const T th = (bi > T(0) ? bi : T(0)) / a;
+                        const int bb = P.basis[i];
+                        if (th < k1 || (th == k1 && bb < k2)) { k1 = th; k2 = bb; p = i; }
+                    }
+                }
+                block_argmin<T, NT>(k1, k2, p, P.sh);
+                l3 = p;
+            }
+        }
+        if (l3 < 0) {
+            sweep2<T, NT>(P, l, e, l2, e2);
+            __syncthreads();
+            P.iters += 2;
+            continue;
+        }
+        if (k1 == T(0)) { ++deg_run; ++P.degp; } else deg_run = 0;
+        // The third pivot's vectors.
+        {
+            const T pe3 = P.pcol3[l3];
+            for (int j = tid; j < C; j += NT) {
+                const T t1 = (l3 == l) ? P.prow[j]
+                                       : fma(-P.pcol[l3], P.prow[j], (j == e) ? T(0) : tab[(int64_t)l3 * ld + j]);
+                const T t = (l3 == l2) ? P.prow2[j] : fma(-P.pcol2[l3], P.prow2[j], (j == e2) ? T(0) : t1);
+                P.prow3[j] = (j == e3) ? T(1) / pe3 : t / pe3;
+            }
+            if (tid == 0) {
+                const int i = m;
+                const T a1 = fma(-P.pcol[i], P.prow[e3], (e3 == e) ? T(0) : tab[(int64_t)i * ld + e3]);
+                P.pcol3[i] = fma(-P.pcol2[i], P.prow2[e3], (e3 == e2) ? T(0) : a1);
+                const int t = P.basis[l3];
+                P.basis[l3] = P.nonb[e3];
+                P.nonb[e3] = t;
+            }
         }
         __syncthreads();
-        P.iters += 2;
+        sweep3<T, NT>(P, l, e, l2, e2, l3, e3);
+        __syncthreads();
+        P.iters += 3;
     }
 }
 
@@ -889,6 +975,8 @@ __global__ __launch_bounds__(NT) void simplex_kernel(SolveArgs a)
         P.prow = reinterpret_cast<T *>(smem + L.prow);
         P.pcol2 = reinterpret_cast<T *>(smem + L.pcol2);
         P.prow2 = reinterpret_cast<T *>(smem + L.prow2);
+        P.pcol3 = reinterpret_cast<T *>(smem + L.pcol3);
+        P.prow3 = reinterpret_cast<T *>(smem + L.prow3);
         if (L.tab > int64_t(a.lds_bytes)) {
             reject_lp<T, NT>(P, a);
             __syncthreads();
