@@ -22,14 +22,17 @@
 //     consecutive degenerate pivots, until a pivot makes progress.
 //   Step 2 (ratio): argmin of max(b_i, 0) / a_ie over rows with a_ie > tol_piv,
 //     ties to the smallest Bland index of the basic variable; none: unbounded.
-//     Wavefront butterfly reductions on (key, Bland index) pairs stand in for
-//     the paper's Data[]/Indices[] arrays, with +inf as the "MAX" sentinel.
+//     Wavefront DPP reductions and ballots on (key, Bland index), then one
+//     slot per wavefront in LDS, stand in for the paper's Data[]/Indices[]
+//     arrays, with +inf as the "MAX" sentinel.
 //   Step 3 (pivot): pivot row / PE; every other row (objective included) minus
 //     a_ie times the new pivot row (Listing 1); the entering column becomes the
 //     leaving variable's column: 1/PE in the pivot row, -a_ie/PE elsewhere.
 //     Every element is rewritten with one fma, the same expression wherever
 //     the tableau lives, so results do not depend on the placement or the
-//     workgroup size.
+//     workgroup size.  Up to three consecutive pivots whose Steps 1-2 can be
+//     taken from the earlier pivots' vectors share one sweep (each element
+//     takes their rules in order, so results are those of separate sweeps).
 // Phase I (Sec. 4) maximises -(sum of artificials) when some row needs one;
 // basic artificials at zero are driven out and redundant rows dropped, then
 // Phase II prices c out over the basis and continues.
@@ -397,7 +400,8 @@ __device__ __forceinline__ int simplex(LP<T, NT> &P, T eps_opt, const SolveParam
         // in row l), so Steps 1 and 2 of the next iteration need only the
         // objective row, one column and the right-hand sides of it, computed
         // here from the pivot's vectors without sweeping the tableau.  When
-        // they find a second pivot both go through one sweep (sweep2).
+        // they find a second pivot both go through one sweep (sweep2), or,
+        // when a third is found the same way, all three (sweep3).
         pivot_vectors<T, NT>(P, l, e, true);
         if (tid == 0) {
             const int t = P.basis[l];
