@@ -73,6 +73,9 @@ def test_uneven_gaussian_subset(ctx):
     assert set(np.unique(st)) >= {0, 1, 2}
     assert np.all(st[bt.meta["infeasible"]] == oracle.INFEASIBLE)
     assert np.all(st[bt.meta["unbounded"]] == oracle.UNBOUNDED)
+    # The workgroup launch takes the CU's LDS share: some tableaux live in LDS
+    # (placement 3), the largest in device-memory slots (placement 2).
+    assert np.any(stats[:, 6] == 3) and np.any(stats[:, 6] == 2)
 
 
 def test_uniform_500x500_hbm(ctx):
