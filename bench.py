@@ -117,7 +117,7 @@ def roofline(per_kernel, dom, lds_bytes, hbm_bytes, peaks, workload_name):
                 lds_traffic=tr["lds"] if tr else None)
     if tr and tr["hbm"]:
         # Measured bytes over the same time: below the algorithmic figure when
-        # pivots are swept in pairs (one pass of the tableau for two pivots).
+        # pivots share sweeps (one pass of the tableau for two or three pivots).
         roof.update(traffic_gb_per_s=tr["hbm"] / dom_s / 1e9, traffic_frac=tr["hbm"] / dom_s / PEAK_HBM)
     return roof
 
